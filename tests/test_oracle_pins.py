@@ -1,0 +1,297 @@
+"""Pins for the FP64 CPU oracle: every check here compares the oracle with
+something other than itself (a closed form, an invariant, an enumeration, a
+library routine on a different formulation, or published known-answer values).
+
+A plausible slip anywhere in the oracle (a dropped term, a diagonal or lower
+triangle read, a wrong weight index, a swapped operand, an off-by-one in the
+permutation loop, a missing "+1" in the p-value) fails at least one test.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def rand_sym(n, seed):
+    return synth.uniform_matrix(n, seed)
+
+
+def weights(sizes):
+    return synth.inv_group_sizes(sizes)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# --- P1: a single group reduces to the total sum of squares over n ---------
+@pytest.mark.parametrize("n", [2, 3, 17, 200])
+def test_single_group_equals_frobenius(n):
+    D = rand_sym(n, 11 + n)
+    g = np.zeros(n, dtype=np.int32)
+    s = oracle.sW(D, g, np.array([1.0 / n]))[0]
+    # ||D||_F^2 counts every off-diagonal pair twice (D symmetric, zero diagonal)
+    fro = np.linalg.norm(D.astype(np.float64)) ** 2 / (2 * n)
+    assert rel(s, fro) < 1e-12
+    assert rel(oracle.sT(D), fro) < 1e-12
+
+
+# --- P2: all singletons: no pair shares a label ------------------------------
+def test_all_singletons_is_zero():
+    n = 64
+    D = rand_sym(n, 5)
+    g = np.arange(n, dtype=np.int32)
+    s = oracle.sW(D, g, np.ones(n))[0]
+    assert s == 0.0
+
+
+# --- P3: relabeling groups by a bijection, weights permuted with it ----------
+def test_label_bijection_invariance():
+    n, sizes = 120, [10, 30, 80]
+    D = rand_sym(n, 7)
+    g = synth.base_labels(sizes)
+    rng = np.random.default_rng(3)
+    g = g[rng.permutation(n)]
+    w = weights(sizes)
+    pi = np.array([2, 0, 1])           # old label -> new label
+    g2 = pi[g].astype(np.int32)
+    w2 = np.empty_like(w)
+    w2[pi] = w
+    a = oracle.sW(D, g, w)[0]
+    b = oracle.sW(D, g2, w2)[0]
+    assert a == b                       # same terms in the same order
+
+
+# --- P4: reordering the objects consistently -----------------------------
+def test_object_reordering_invariance():
+    n, sizes = 150, [20, 50, 80]
+    D = rand_sym(n, 9)
+    g = synth.base_labels(sizes)[np.random.default_rng(1).permutation(n)]
+    sigma = np.random.default_rng(2).permutation(n)
+    D2 = np.ascontiguousarray(D[np.ix_(sigma, sigma)])
+    g2 = g[sigma]
+    w = weights(sizes)
+    assert rel(oracle.sW(D2, g2, w)[0], oracle.sW(D, g, w)[0]) < 1e-13
+
+
+# --- P5: constant off-diagonal distance ------------------------------------
+def test_constant_matrix_closed_form_and_ties():
+    sizes = [8, 16, 32, 8]                # powers of two: every weight exact
+    n, k, c = sum(sizes), len(sizes), 0.5
+    D = np.full((n, n), c, dtype=np.float32)
+    np.fill_diagonal(D, 0.0)
+    base = synth.base_labels(sizes)
+    perms = oracle.permute(base, 50, seed=77)
+    s = oracle.sW(D, np.vstack([base, perms]), weights(sizes))
+    # sum_g w_g n_g (n_g - 1)/2 * c^2 = c^2 (n - k)/2 for w_g = 1/n_g
+    assert np.all(s == c * c * (n - k) / 2)
+    # every permutation ties with the observed grouping, so p = 1
+    f = oracle.F(s, oracle.sT(D), n, k)
+    assert oracle.pvalue(f[0], f[1:]) == 1.0
+    assert oracle.pvalue_sW(s[0], s[1:]) == 1.0
+
+
+# --- P6: Euclidean distances: Huygens/Koenig decomposition -----------------
+def test_euclidean_huygens_closed_form():
+    n, sizes = 300, [50, 100, 150]
+    x = synth.euclid_points(n, 42, dims=8)
+    D = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)).astype(np.float32)
+    np.fill_diagonal(D, 0.0)
+    g = synth.base_labels(sizes)[np.random.default_rng(4).permutation(n)]
+    s = oracle.sW(D, g, weights(sizes))[0]
+    # sum_g (1/n_g) sum_{i<j in g} ||x_i - x_j||^2 = sum_g sum_{i in g} ||x_i - mean_g||^2
+    closed = sum(((x[g == q] - x[g == q].mean(0)) ** 2).sum() for q in range(3))
+    assert rel(s, closed) < 2e-7        # fp32 storage of d is the only error
+
+
+# --- P7: tiny n, all n! relabelings ----------------------------------------
+def test_enumeration_mean_and_submatrix_formula():
+    sizes = [2, 2, 3]
+    n, k = 7, 3
+    D = rand_sym(n, 21)
+    base = synth.base_labels(sizes)
+    allg = np.array([base[list(pi)] for pi in itertools.permutations(range(n))], dtype=np.int32)
+    w = weights(sizes)
+    s = oracle.sW(D, allg, w)
+    D2 = D.astype(np.float64) ** 2
+    # (i) per-group submatrix sums, an independent formulation
+    for row in range(0, allg.shape[0], 97):
+        g = allg[row]
+        sub = sum(w[q] * np.triu(D2[np.ix_(g == q, g == q)], 1).sum() for q in range(k))
+        assert rel(s[row], sub) < 1e-13
+    # (ii) the mean over all n! relabelings is s_T (n - k)/(n - 1) for w = 1/n_g
+    assert rel(s.mean(), oracle.sT(D) * (n - k) / (n - 1)) < 1e-13
+    # (iii) exact permutation p-value over the enumeration
+    f = oracle.F(s, oracle.sT(D), n, k)
+    obs = 0
+    count = sum(1 for v in f if v >= f[obs])
+    assert oracle.pvalue(f[obs], f) == (1 + count) / (1 + len(f))
+
+
+# --- P8: dyadic inputs: the FP64 result is the exact rational --------------
+def test_dyadic_exact_against_fractions():
+    sizes = [4, 8, 16, 4]
+    n = sum(sizes)
+    D = synth.dyadic_matrix(n, 5)
+    base = synth.base_labels(sizes)
+    perms = oracle.permute(base, 6, seed=9)
+    w = weights(sizes)
+    s = oracle.sW(D, perms, w)
+    for p in range(perms.shape[0]):
+        g = perms[p]
+        exact = Fraction(0)
+        for i in range(n):
+            for j in range(i + 1, n):
+                if g[i] == g[j]:
+                    exact += Fraction(float(D[i, j])) ** 2 * Fraction(1, sizes[g[i]])
+        assert Fraction(s[p]) == exact
+
+
+# --- P9: Algorithm 1 order == Algorithm 2 tiled order == dense product ------
+@pytest.mark.parametrize("tile", [1, 3, 7, 64, 500])
+def test_algorithm2_and_dense_formulation(tile):
+    n, sizes = 500, [60, 140, 300]
+    D = rand_sym(n, 31)
+    perms = oracle.permute(synth.base_labels(sizes), 5, seed=8)
+    w = weights(sizes)
+    a1 = oracle.sW(D, perms, w)
+    a2 = oracle.sW_tiled(D, perms, w, tile)
+    D2 = D.astype(np.float64) ** 2
+    for p in range(perms.shape[0]):
+        G = np.eye(3)[perms[p]]                     # n x k one-hot
+        dense = 0.5 * float(np.sum(w * np.diag(G.T @ D2 @ G)))
+        assert rel(a1[p], dense) < 1e-13
+        assert rel(a2[p], a1[p]) < 1e-13
+
+
+# --- only the strict upper triangle is read --------------------------------
+def test_reads_strict_upper_triangle_only():
+    n, sizes = 90, [30, 60]
+    D = rand_sym(n, 13)
+    g = oracle.permute(synth.base_labels(sizes), 3, seed=1)
+    w = weights(sizes)
+    ref = oracle.sW(D, g, w)
+    E = D.copy()
+    E[np.tril_indices(n)] = np.nan                 # lower triangle and diagonal
+    assert np.array_equal(oracle.sW(E, g, w), ref)
+    assert np.array_equal(oracle.sW_tiled(E, g, w, 16), oracle.sW_tiled(D, g, w, 16))
+    assert oracle.sT(E) == oracle.sT(D)
+
+
+# --- P10: F-based and s_W-based p-values agree --------------------------------
+def test_pvalue_monotone_equivalence():
+    n, sizes = 200, [50, 70, 80]
+    D = rand_sym(n, 17)
+    r = oracle.permanova(D, synth.base_labels(sizes), 199, seed=5)
+    p_sw = oracle.pvalue_sW(r["sW_obs"], r["sW_perm"])
+    assert r["p"] == p_sw
+    assert any(abs(r["p"] * 200 - m) < 1e-9 for m in range(1, 201))
+    # F strictly decreasing in s_W
+    order = np.argsort(r["sW_perm"])
+    assert np.all(np.diff(r["F_perm"][order]) <= 0)
+
+
+# --- P11: linearity in the weights; within + between = total ---------------
+def test_linearity_and_complement():
+    n, sizes = 160, [40, 50, 70]
+    D = rand_sym(n, 23)
+    g = oracle.permute(synth.base_labels(sizes), 1, seed=2)[0]
+    w = np.array([0.3, 1.7, 0.9])
+    S = [oracle.sW(D, g, np.eye(3)[q])[0] for q in range(3)]
+    assert rel(oracle.sW(D, g, w)[0], float(np.dot(w, S))) < 1e-13
+    within = oracle.sW(D, g, np.ones(3))[0]
+    between = oracle.between_unweighted(D, g)
+    assert rel(within + between, oracle.sT(D) * n) < 1e-13
+
+
+# --- a hand-worked example ---------------------------------------------------
+def test_hand_example_sW_sT_F():
+    # objects 0,1 in group 0 and 2,3 in group 1; d01 = 1, d23 = 2, all else 3
+    D = np.full((4, 4), 3.0, dtype=np.float32)
+    np.fill_diagonal(D, 0.0)
+    D[0, 1] = D[1, 0] = 1.0
+    D[2, 3] = D[3, 2] = 2.0
+    g = np.array([0, 0, 1, 1], dtype=np.int32)
+    s = oracle.sW(D, g, [0.5, 0.5])[0]
+    assert s == 0.5 * 1 + 0.5 * 4                     # 2.5
+    t = oracle.sT(D)
+    assert t == (1 + 4 + 4 * 9) / 4                   # 10.25
+    f = oracle.F([s], t, 4, 2)[0]
+    assert f == (7.75 / 1) / (2.5 / 2)                # 6.2
+
+
+def test_pvalue_counts_and_degenerate_cases():
+    assert oracle.pvalue(2.0, [1.0, 2.0, 3.0, np.nan]) == 3 / 5
+    assert oracle.pvalue_sW(2.0, [1.0, 2.0, 3.0, np.nan]) == 3 / 5
+    assert math.isnan(oracle.pvalue(1.0, np.array([], dtype=np.float64)))
+    assert np.isnan(oracle.F([1.0], 2.0, 10, 1)[0])       # k = 1
+    assert np.isnan(oracle.F([1.0], 2.0, 5, 5)[0])        # k = n
+    assert oracle.F([0.0], 2.0, 10, 2)[0] == np.inf        # s_W = 0, s_A > 0
+
+
+# --- permutation generator ----------------------------------------------------
+def test_splitmix64_known_answers():
+    # published SplitMix64 output for state 0 (reference implementation of
+    # Steele, Lea & Flood 2014; the same values java.util.SplittableRandom gives)
+    kat = [int(line.split()[0], 16) for line in
+           open(__file__.replace("test_oracle_pins.py", "golden/splitmix64_seed0.txt"))
+           if line.strip() and not line.startswith("#")]
+    assert oracle.splitmix64_stream(0, len(kat)) == kat
+
+
+def test_bounded_power_of_two_is_top_bits():
+    # for s = 2^b Lemire's method never rejects and returns the top b bits
+    for b in (1, 5, 16, 31):
+        st = 0x1234_5678_9ABC_DEF0
+        raw = oracle.splitmix64_stream(st, 50)
+        got = oracle.bounded(st, 1 << b, 50)
+        assert got == [(x >> 32) >> (32 - b) for x in raw]
+    assert oracle.bounded(99, 1, 20) == [0] * 20
+
+
+def test_bounded_uniform_with_rejection_range():
+    s = 3 * (1 << 29) + 7                       # large, non-power-of-two bound
+    v = np.array(oracle.bounded(2024, s, 60000), dtype=np.float64)
+    assert v.min() >= 0 and v.max() < s
+    hist = np.histogram(v, bins=12, range=(0, s))[0]
+    chi2 = ((hist - 5000.0) ** 2 / 5000.0).sum()
+    assert chi2 < 40                             # 11 dof, p ~ 1e-4
+
+
+def test_permutations_are_uniform_shuffles():
+    base = np.array([0, 1, 2, 3], dtype=np.int32)
+    P = 24000
+    perms = oracle.permute(base, P, seed=123)
+    assert np.all(np.sort(perms, axis=1) == base)
+    codes = (perms * np.array([64, 16, 4, 1])).sum(1)
+    counts = np.unique(codes, return_counts=True)[1]
+    assert len(counts) == 24
+    chi2 = ((counts - 1000.0) ** 2 / 1000.0).sum()
+    assert chi2 < 60                             # 23 dof, p ~ 5e-5
+
+
+def test_permutation_multiset_and_stream_independence():
+    sizes = [3, 5, 9]
+    base = synth.base_labels(sizes)
+    a = oracle.permute(base, 40, seed=7)
+    b = oracle.permute(base, 40, seed=7, nthreads=1)
+    assert np.array_equal(a, b)                  # independent of thread count
+    for row in a:
+        assert np.array_equal(np.bincount(row, minlength=3), sizes)
+    assert len({tuple(r) for r in a}) > 35       # rows differ from each other
+    c = oracle.permute(base, 40, seed=8)
+    assert not np.array_equal(a, c)
+
+
+def test_permutation_golden_fixture():
+    path = __file__.replace("test_oracle_pins.py", "golden/permute_n16_P4_seed3000.txt")
+    rows = [list(map(int, line.split())) for line in open(path)
+            if line.strip() and not line.startswith("#")]
+    base = np.array(rows[0], dtype=np.int32)
+    got = oracle.permute(base, len(rows) - 1, seed=3000)
+    assert got.tolist() == rows[1:]
