@@ -1,0 +1,170 @@
+/*
+ * pstat -- PERMANOVA's permuted within-group statistic s_W on AMD MI355X (gfx950).
+ *
+ * C ABI of libpstat.so.  Every entry point is extern "C", returns an int status
+ * (PSTAT_OK or a negative PSTAT_E* code), never throws, and leaves its outputs
+ * unwritten when it returns an error.  pstat_last_error() gives a readable
+ * reason (thread-local; includes the HIP error string where one exists).
+ *
+ * Memory.  Unless stated otherwise every array argument is a DEVICE pointer
+ * (hipMalloc'd or a torch CUDA tensor's storage) owned by the caller; the library
+ * never frees or keeps a caller pointer after a call returns, except a matrix
+ * registered with pstat_matrix_register, which must stay alive until
+ * pstat_matrix_release.  A host pointer passed where a device pointer is
+ * required gives PSTAT_EPTR.
+ *
+ * Streams.  Work is enqueued on the calling thread's stream (pstat_set_stream;
+ * default: the null stream).  Results are valid once the caller synchronises
+ * that stream.  Calls that must look at a value on the device before they can
+ * decide what to do (label validation in pstat_sW, the tie recheck in
+ * pstat_permanova) synchronise the stream themselves and say so below.
+ *
+ * Scratch.  The library needs device scratch (staged labels, per-block
+ * partials, pre-squared matrix tiles).  If the thread has set a workspace with
+ * pstat_set_workspace it is used (PSTAT_ENOMEM if too small, see
+ * pstat_workspace_bytes); otherwise the library allocates and caches its own.
+ *
+ * Layouts.  mat is n x n float32, row-major, 64-bit element offsets
+ * (row * n + col); only the strict upper triangle (col > row) is ever read.
+ * groupings is int32, permutation-major: row p (n labels) starts at p * n.
+ * Labels are group indices 0 <= g < k (k <= 65535) and index inv_group_sizes.
+ */
+#ifndef PSTAT_H
+#define PSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PSTAT_OK 0
+#define PSTAT_EINVAL (-1)  /* bad size or argument                         */
+#define PSTAT_ELABEL (-2)  /* a label < 0 or >= 65535                      */
+#define PSTAT_EDOMAIN (-3) /* F undefined: k < 2 or n <= k                 */
+#define PSTAT_ENOMEM (-4)  /* workspace too small / device allocation fail */
+#define PSTAT_EHIP (-5)    /* a HIP runtime call failed                    */
+#define PSTAT_EPTR (-6)    /* pointer is not device-accessible memory      */
+#define PSTAT_ESTATE (-7)  /* pstat_init not called on this thread/device  */
+
+/* ---- computation forms of s_W ------------------------------------------ */
+#define PSTAT_PATH_AUTO (-1)           /* the tuned default                */
+#define PSTAT_PATH_PLAIN_F32 0         /* VALU kernel, FP32 row segments   */
+#define PSTAT_PATH_MFMA_BF16 1         /* MFMA, D^2 in BF16                */
+#define PSTAT_PATH_MFMA_F16 2          /* MFMA, D^2 in FP16                */
+#define PSTAT_PATH_MFMA_SPLIT_BF16 3   /* MFMA, D^2 as BF16 hi + BF16 lo   */
+#define PSTAT_PATH_PLAIN_F64 4         /* VALU kernel, FP64 throughout     */
+#define PSTAT_N_PATHS 5
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int pstat_version(void);
+
+/* Text of the last error on this thread ("" if none).  Never NULL. */
+const char *pstat_last_error(void);
+
+/* Make `device` current for this thread, read its properties and prepare the
+ * library's per-device state.  Must precede every other call on the thread. */
+int pstat_init(int device);
+
+/* Stream (a hipStream_t, NULL = null stream) for this thread's later calls. */
+int pstat_set_stream(void *hip_stream);
+
+/* Form used by pstat_sW / pstat_sW_k / pstat_permanova on this thread.
+ * PSTAT_PATH_AUTO (default) = the tuned choice for the problem shape. */
+int pstat_set_path(int path);
+
+/* Tuning of one path for this thread: `tile` and `batch` override the tuned
+ * values (0 = keep the tuned value).  Plain paths: tile = square tile edge
+ * (32 or 64), batch = permutation lanes per work-group (64, 128 or 256).  MFMA
+ * paths: tile = K-chunk length in columns (multiple of 64, 0 = tuned), batch =
+ * N columns per work-group (128 or 256).  Invalid values give PSTAT_EINVAL. */
+int pstat_set_tuning(int path, int tile, int batch);
+
+/* Caller-owned device workspace for this thread (NULL, 0 = library-managed). */
+int pstat_set_workspace(void *dev_ptr, size_t bytes);
+
+/* Workspace pstat_sW_k needs for this shape and path (bytes), 0 on bad input. */
+size_t pstat_workspace_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int path);
+
+/* ---- the statistic (section 2, Algorithm 1) ------------------------------ */
+
+/* out[p] = s_W of grouping row p, p = 0 .. n_perms-1:
+ *   s_W = sum over 0 <= i < j < n with g[i] == g[j] of mat[i*n+j]^2 * inv_group_sizes[g[i]],
+ * the paper's permanova_f_stat_sW_T with the paper's argument order.  k is
+ * found as 1 + the largest label, so inv_group_sizes must hold at least that
+ * many FP64 weights (normally 1/n_g).  Validates every label first and
+ * SYNCHRONISES the stream once to read the result: PSTAT_ELABEL on a label
+ * outside [0, 65535).  n >= 2, n_perms >= 0 (0: nothing to do). */
+int pstat_sW(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+             const double *inv_group_sizes, double *out);
+
+/* pstat_sW with the number of groups given (labels must lie in [0, n_groups)):
+ * no synchronisation.  A label out of range is reported asynchronously: the
+ * affected out[p] are set to NaN and the next pstat_check_labels on this
+ * thread returns PSTAT_ELABEL. */
+int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+               int32_t n_groups, const double *inv_group_sizes, double *out);
+
+/* PSTAT_OK if no out-of-range label was seen by this thread's pstat_sW_k calls
+ * since the previous check, else PSTAT_ELABEL.  Synchronises the stream. */
+int pstat_check_labels(void);
+
+/* ---- the steps around it (section 2: "before and after") ---------------- */
+
+/* *s_T = (1/n) * sum_{i<j} mat[i*n+j]^2, FP64 (device scalar). */
+int pstat_sT(const float *mat, int64_t n, double *s_T);
+
+/* F[i] = ((s_T - s_W[i]) / (k-1)) / (s_W[i] / (n-k)), FP64; s_T is a device
+ * scalar.  PSTAT_EDOMAIN if k < 2 or n <= k. */
+int pstat_F(const double *s_W, int64_t count, const double *s_T, int64_t n, int32_t k,
+            double *F);
+
+/* *p = (1 + #{q : s_W_perm[q] <= *s_W_obs}) / (1 + n_perms), FP64, device
+ * scalars; equal to the count of F_q >= F_obs for k >= 2, n > k, s_W > 0.
+ * n_perms = 0 gives NaN. */
+int pstat_pvalue(const double *s_W_obs, const double *s_W_perm, int64_t n_perms, double *p);
+
+/* inv[g] = 1 / #{i : grouping[i] == g} for g < n_groups (0 for an empty group),
+ * FP64 (the weights PERMANOVA passes as inv_group_sizes). */
+int pstat_group_weights(const int32_t *grouping, int64_t n, int32_t n_groups, double *inv);
+
+/* groupings[p*n + i], p < n_perms: Durstenfeld's Fisher-Yates shuffle of base
+ * (n labels, device) for permutation p, driven by SplitMix64 started at
+ * mix(seed XOR mix(p + 1)) with Lemire's bounded draw -- the random relabeling
+ * of the permutation test (section 1).  Labels must lie in [0, 65535). */
+int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed,
+                  int32_t *groupings);
+
+/* The whole permutation test on one matrix, all on the device:
+ * weights 1/n_g from `grouping` (n_groups groups), n_perms shuffles
+ * (pstat_permute with `seed`), s_W of the observed grouping and of every
+ * shuffle, s_T, F and p.  Permutations whose s_W lies within the path's error
+ * band of the observed value are recomputed with PSTAT_PATH_PLAIN_F64 before
+ * counting; this SYNCHRONISES the stream once.  result (device, 4 doubles) =
+ * {F_obs, p, s_W_obs, s_T}; sW_all (device, n_perms + 1 doubles, may be NULL)
+ * receives s_W of the observed grouping then of each shuffle; n_rechecked
+ * (host, may be NULL) receives how many permutations were recomputed. */
+int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_t n_groups,
+                    int64_t n_perms, uint64_t seed, double *result, double *sW_all,
+                    int64_t *n_rechecked);
+
+/* ---- resident matrices -------------------------------------------------- */
+
+/* Register a resident matrix for repeated tests: the library keeps the MFMA
+ * forms' pre-squared tiles (when `path` is an MFMA path) so later calls skip
+ * that staging.  `mat` must stay valid until release.  *handle > 0. */
+int pstat_matrix_register(const float *mat, int64_t n, int path, int64_t *handle);
+int pstat_matrix_release(int64_t handle);
+
+/* pstat_sW_k on a registered matrix with that registration's path. */
+int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perms,
+                        int32_t n_groups, const double *inv_group_sizes, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSTAT_H */

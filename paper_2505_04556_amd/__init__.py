@@ -1,0 +1,280 @@
+"""PERMANOVA's permuted within-group statistic s_W on AMD MI355X (gfx950).
+
+Thin Python binding of ``libpstat.so`` (C ABI in ``include/pstat.h``).  Every
+function has the C entry point's name and only marshals arguments: torch CUDA
+tensors in, device pointers and sizes out, the library's status code turned
+into an exception.  All computation runs in the library's HIP kernels; there
+is no CPU fallback, and importing this package fails loudly if the library has
+not been built (``python -m paper_2505_04556_amd.build``).
+
+torch supplies device memory and the current stream only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpstat.so")
+
+PSTAT_OK = 0
+PSTAT_EINVAL = -1
+PSTAT_ELABEL = -2
+PSTAT_EDOMAIN = -3
+PSTAT_ENOMEM = -4
+PSTAT_EHIP = -5
+PSTAT_EPTR = -6
+PSTAT_ESTATE = -7
+
+PSTAT_PATH_AUTO = -1
+PSTAT_PATH_PLAIN_F32 = 0
+PSTAT_PATH_MFMA_BF16 = 1
+PSTAT_PATH_MFMA_F16 = 2
+PSTAT_PATH_MFMA_SPLIT_BF16 = 3
+PSTAT_PATH_PLAIN_F64 = 4
+PATH_NAMES = {
+    PSTAT_PATH_PLAIN_F32: "plain_f32",
+    PSTAT_PATH_MFMA_BF16: "mfma_bf16",
+    PSTAT_PATH_MFMA_F16: "mfma_f16",
+    PSTAT_PATH_MFMA_SPLIT_BF16: "mfma_split_bf16",
+    PSTAT_PATH_PLAIN_F64: "plain_f64",
+}
+PATH_IDS = {v: k for k, v in PATH_NAMES.items()}
+
+_CODE_NAMES = {
+    PSTAT_EINVAL: "EINVAL", PSTAT_ELABEL: "ELABEL", PSTAT_EDOMAIN: "EDOMAIN",
+    PSTAT_ENOMEM: "ENOMEM", PSTAT_EHIP: "EHIP", PSTAT_EPTR: "EPTR", PSTAT_ESTATE: "ESTATE",
+}
+
+
+class PstatError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_CODE_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_04556_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i64, _i32, _u64, _int, _size = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_size_t)
+_SIGS = {
+    "pstat_version": ([], _int),
+    "pstat_last_error": ([], ctypes.c_char_p),
+    "pstat_init": ([_int], _int),
+    "pstat_set_stream": ([_P], _int),
+    "pstat_set_path": ([_int], _int),
+    "pstat_set_tuning": ([_int, _int, _int], _int),
+    "pstat_set_workspace": ([_P, _size], _int),
+    "pstat_workspace_bytes": ([_i64, _i64, _i32, _int], _size),
+    "pstat_sW": ([_P, _i64, _P, _i64, _P, _P], _int),
+    "pstat_sW_k": ([_P, _i64, _P, _i64, _i32, _P, _P], _int),
+    "pstat_check_labels": ([], _int),
+    "pstat_sT": ([_P, _i64, _P], _int),
+    "pstat_F": ([_P, _i64, _P, _i64, _i32, _P], _int),
+    "pstat_pvalue": ([_P, _P, _i64, _P], _int),
+    "pstat_group_weights": ([_P, _i64, _i32, _P], _int),
+    "pstat_permute": ([_P, _i64, _i64, _u64, _P], _int),
+    "pstat_permanova": ([_P, _i64, _P, _i32, _i64, _u64, _P, _P, ctypes.POINTER(_i64)], _int),
+    "pstat_matrix_register": ([_P, _i64, _int, ctypes.POINTER(_i64)], _int),
+    "pstat_matrix_release": ([_i64], _int),
+    "pstat_sW_registered": ([_i64, _P, _i64, _i32, _P, _P], _int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+_tls = threading.local()
+
+
+def _check(rc: int) -> None:
+    if rc != PSTAT_OK:
+        raise PstatError(rc, _lib.pstat_last_error().decode(errors="replace"))
+
+
+def _ready(device: torch.device) -> None:
+    """pstat_init once per thread and device; current torch stream every call."""
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if getattr(_tls, "device", None) != idx:
+        _check(_lib.pstat_init(idx))
+        _tls.device = idx
+    _check(_lib.pstat_set_stream(ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise PstatError(PSTAT_EPTR, f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise PstatError(PSTAT_EINVAL, f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise PstatError(PSTAT_EINVAL, f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def pstat_version() -> int:
+    return int(_lib.pstat_version())
+
+
+def pstat_set_path(path) -> None:
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.pstat_set_path(p))
+
+
+def pstat_set_tuning(path, tile: int = 0, batch: int = 0) -> None:
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.pstat_set_tuning(p, int(tile), int(batch)))
+
+
+def pstat_set_workspace(ws: torch.Tensor | None) -> None:
+    if ws is None:
+        _check(_lib.pstat_set_workspace(None, 0))
+        return
+    _ready(ws.device)
+    _check(_lib.pstat_set_workspace(_dev(ws, torch.uint8, "workspace"), ws.numel()))
+
+
+def pstat_workspace_bytes(n: int, n_perms: int, n_groups: int, path=PSTAT_PATH_AUTO) -> int:
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    return int(_lib.pstat_workspace_bytes(n, n_perms, n_groups, p))
+
+
+def pstat_sW(mat: torch.Tensor, groupings: torch.Tensor, inv_group_sizes: torch.Tensor,
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """s_W of every grouping row (validates labels; synchronises once)."""
+    n = mat.shape[0]
+    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=mat.device)
+    _ready(mat.device)
+    _check(_lib.pstat_sW(_dev(mat, torch.float32, "mat"), n,
+                         _dev(groupings, torch.int32, "groupings"), P,
+                         _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
+                         _dev(out, torch.float64, "out")))
+    return out
+
+
+def pstat_sW_k(mat, groupings, n_groups: int, inv_group_sizes, out=None) -> torch.Tensor:
+    """s_W with the number of groups given; asynchronous."""
+    n = mat.shape[0]
+    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=mat.device)
+    _ready(mat.device)
+    _check(_lib.pstat_sW_k(_dev(mat, torch.float32, "mat"), n,
+                           _dev(groupings, torch.int32, "groupings"), P, int(n_groups),
+                           _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
+                           _dev(out, torch.float64, "out")))
+    return out
+
+
+def pstat_check_labels() -> None:
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.pstat_check_labels())
+
+
+def pstat_sT(mat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=mat.device)
+    _ready(mat.device)
+    _check(_lib.pstat_sT(_dev(mat, torch.float32, "mat"), mat.shape[0],
+                         _dev(out, torch.float64, "s_T")))
+    return out
+
+
+def pstat_F(s_W: torch.Tensor, s_T: torch.Tensor, n: int, k: int,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty_like(s_W)
+    _ready(s_W.device)
+    _check(_lib.pstat_F(_dev(s_W, torch.float64, "s_W"), s_W.numel(),
+                        _dev(s_T, torch.float64, "s_T"), int(n), int(k),
+                        _dev(out, torch.float64, "F")))
+    return out
+
+
+def pstat_pvalue(s_W_obs: torch.Tensor, s_W_perm: torch.Tensor,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=s_W_obs.device)
+    _ready(s_W_obs.device)
+    perm_ptr = _dev(s_W_perm, torch.float64, "s_W_perm") if s_W_perm.numel() else None
+    _check(_lib.pstat_pvalue(_dev(s_W_obs, torch.float64, "s_W_obs"), perm_ptr,
+                             s_W_perm.numel(), _dev(out, torch.float64, "p")))
+    return out
+
+
+def pstat_group_weights(grouping: torch.Tensor, n_groups: int,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(n_groups, dtype=torch.float64, device=grouping.device)
+    _ready(grouping.device)
+    _check(_lib.pstat_group_weights(_dev(grouping, torch.int32, "grouping"), grouping.numel(),
+                                    int(n_groups), _dev(out, torch.float64, "inv")))
+    return out
+
+
+def pstat_permute(base: torch.Tensor, n_perms: int, seed: int,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    n = base.numel()
+    if out is None:
+        out = torch.empty((n_perms, n), dtype=torch.int32, device=base.device)
+    _ready(base.device)
+    _check(_lib.pstat_permute(_dev(base, torch.int32, "base"), n, int(n_perms),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, _dev(out, torch.int32, "groupings")))
+    return out
+
+
+def pstat_permanova(mat: torch.Tensor, grouping: torch.Tensor, n_groups: int, n_perms: int,
+                    seed: int, result: torch.Tensor | None = None,
+                    sW_all: torch.Tensor | None = None) -> tuple[torch.Tensor, int]:
+    """The whole test.  Returns (result = [F_obs, p, s_W_obs, s_T], n_rechecked)."""
+    if result is None:
+        result = torch.empty(4, dtype=torch.float64, device=mat.device)
+    _ready(mat.device)
+    rechecked = _i64(0)
+    sw_ptr = _dev(sW_all, torch.float64, "sW_all") if sW_all is not None else None
+    _check(_lib.pstat_permanova(_dev(mat, torch.float32, "mat"), mat.shape[0],
+                                _dev(grouping, torch.int32, "grouping"), int(n_groups),
+                                int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                _dev(result, torch.float64, "result"), sw_ptr,
+                                ctypes.byref(rechecked)))
+    return result, int(rechecked.value)
+
+
+def pstat_matrix_register(mat: torch.Tensor, path=PSTAT_PATH_AUTO) -> int:
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    _ready(mat.device)
+    h = _i64(0)
+    _check(_lib.pstat_matrix_register(_dev(mat, torch.float32, "mat"), mat.shape[0], p,
+                                      ctypes.byref(h)))
+    return int(h.value)
+
+
+def pstat_matrix_release(handle: int) -> None:
+    _check(_lib.pstat_matrix_release(int(handle)))
+
+
+def pstat_sW_registered(handle: int, groupings: torch.Tensor, n_groups: int,
+                        inv_group_sizes: torch.Tensor, out: torch.Tensor | None = None):
+    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=groupings.device)
+    _ready(groupings.device)
+    _check(_lib.pstat_sW_registered(int(handle), _dev(groupings, torch.int32, "groupings"), P,
+                                    int(n_groups),
+                                    _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
+                                    _dev(out, torch.float64, "out")))
+    return out
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS)

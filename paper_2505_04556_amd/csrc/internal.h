@@ -1,0 +1,117 @@
+// Internal interfaces between the library's translation units.  Not installed;
+// the public ABI is include/pstat.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pstat {
+
+// Label value used for padding rows, columns and permutation lanes; it never
+// equals a real label (real labels are < 65535).
+constexpr uint16_t kPadLabel = 0xFFFF;
+constexpr int kMaxGroups = 65535;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Number of tiles of an upper-triangular tiling with nt tiles per side.
+inline int64_t tri_count(int64_t nt) { return nt * (nt + 1) / 2; }
+
+// ---- staging (k_stage.hip) ------------------------------------------------
+// int32 [.][n] -> u16 [n_pad][P_pad] (object-major), pads with kPadLabel;
+// staged permutation q is row rows[q] of g (row q when rows is NULL).
+// Labels outside [0, limit) set bad_perm[q] = 1 and *err_flag |= 1; *max_label
+// receives the largest label seen (atomicMax; the caller sets it to -1 first).
+void launch_stage_labels_om(const int32_t *g, const int32_t *rows, int64_t n, int64_t P,
+                            int64_t n_pad, int64_t P_pad, int32_t limit, uint16_t *out,
+                            uint8_t *bad_perm, int32_t *err_flag, int32_t *max_label,
+                            hipStream_t s);
+// Range check and maximum of `count` int32 labels (no staging).
+void launch_scan_labels(const int32_t *g, int64_t count, int32_t limit, int32_t *err_flag,
+                        int32_t *max_label, hipStream_t s);
+// int32 [P][n] -> u16 [P_pad][n_pad] (permutation-major), same checks.
+void launch_stage_labels_pm(const int32_t *g, int64_t n, int64_t P, int64_t n_pad,
+                            int64_t P_pad, int32_t limit, uint16_t *out, uint8_t *bad_perm,
+                            int32_t *err_flag, int32_t *max_label, hipStream_t s);
+void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s);
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_t *counts,
+                          double *inv, hipStream_t s);
+// s_T: per-block FP64 partial sums of d^2 over the strict upper triangle,
+// then a fixed-order final sum divided by n.
+int64_t sT_partials_count(int64_t n);
+void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s);
+
+// ---- plain kernel (k_plain.hip) -------------------------------------------
+struct PlainPlan {
+    int tile;        // square tile edge T
+    int lanes;       // permutation lanes per work-group (64 * waves)
+    int64_t n_t;     // tiles per side
+    int64_t n_tiles; // upper-triangle tiles
+    int64_t chunks;  // tile chunks (one partial row each)
+    int64_t tiles_per_chunk;
+    int64_t pgroups; // permutation groups
+    int64_t P_pad;   // permutations rounded up to `lanes`
+    int64_t n_pad;   // n rounded up to T
+};
+// plan_P (>= P, or 0 for P) sets the chunk count, so a plan for fewer
+// permutations than plan_P never needs more scratch than one for plan_P.
+PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu, int64_t plan_P = 0);
+// partial[chunk][P_pad] FP64 from u16 [n_pad][P_pad] labels.  Perm lane q of
+// the label table is permutation q.  f64 selects the FP64 instantiation.
+int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
+                 const uint16_t *lab_om, const double *w, int32_t k, double *partial,
+                 hipStream_t s);
+
+// ---- MFMA kernels (k_mfma.hip) ---------------------------------------------
+struct MfmaPlan {
+    int dtype;        // 0 bf16, 1 f16, 2 split bf16 (hi, lo)
+    int64_t n_pad;    // n rounded up to 128 (panel height)
+    int64_t panels;   // row panels of 128 rows
+    int64_t kb_total; // 64-column K blocks in a row: n_pad / 64
+    int64_t kchunk;   // K blocks per work item
+    int64_t items;    // (panel, K chunk) work items
+    int ncols;        // N columns per work-group
+    int64_t N;        // k * P (columns)
+    int64_t nblocks;  // ceil(N / ncols)
+    int64_t P_pad;    // permutation rows of the staged label table
+    size_t tile_bytes;// bytes of the pre-squared tile storage (all components)
+};
+MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, int ncols,
+                   int n_cu);
+size_t mfma_tile_bytes(int64_t n, int dtype);
+// Pre-pass: strict-upper d^2 of 128-row panels into MFMA fragment order.
+void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s);
+size_t mfma_table_bytes(const MfmaPlan &pl);
+// z[item][P][k] FP32 sums of the (G^T U G) diagonal per (panel, K chunk) item;
+// tab is scratch for the item table (mfma_table_bytes).
+int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
+                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s);
+
+// ---- reductions (k_reduce.hip) ---------------------------------------------
+// out[p] = sum_chunk partial[chunk][p] (fixed order); NaN where bad_perm[p].
+void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, int64_t P,
+                         const uint8_t *bad_perm, double *out, hipStream_t s);
+// out[p] = sum_g w[g] * sum_item z[item][p][g] (FP64, fixed order).
+void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
+                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s);
+void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,
+              double *F, hipStream_t s);
+void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,
+                   hipStream_t s);
+// Flag permutations with |sW[q] - sW_obs| <= band * |sW_obs| (q in 1..P of
+// sW_all) into list (1-based indices into sW_all); *count = number flagged.
+void launch_flag_ties(const double *sW_all, int64_t P, double band, int32_t *list,
+                      int32_t *count, hipStream_t s);
+void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *sW_all,
+                    hipStream_t s);
+void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32_t k,
+                        const double *p, double *result, hipStream_t s);
+
+// ---- permutation generator (k_permute.hip) -----------------------------------
+int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
+                   int32_t *out, size_t lds_limit, hipStream_t s);
+
+} // namespace pstat

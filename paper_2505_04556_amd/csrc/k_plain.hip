@@ -1,0 +1,176 @@
+// Plain (VALU) form of s_W: one permutation per lane.
+//
+// The strict upper triangle of D is cut into T x T tiles (I <= J; the diagonal
+// tiles are masked to col > row, which is Algorithm 2's column start of
+// section 2).  A work-group owns LANES permutations (one per lane) and a
+// contiguous run of tiles.  For each tile it stages d^2 into LDS once; every
+// lane then walks the whole tile against its own permutation's labels, which
+// sit in registers for the tile's columns.  The LDS reads use one address per
+// wave (broadcast), so a staged tile is reused by all LANES permutations and D
+// streams from HBM once per LANES permutations instead of once per
+// permutation.  Per row segment the matching d^2 are summed in Acc (FP32 or
+// FP64) and then multiplied once by that row's group weight in FP64 --
+// Algorithm 2's hoisting of inv_group_sizes -- into a per-lane FP64 total.
+// Lanes never share a sum, so no cross-lane reduction is needed; each
+// work-group writes one FP64 partial per permutation and a fixed-order FP64
+// reduction combines them.
+#include "internal.h"
+
+namespace pstat {
+
+namespace {
+
+constexpr int kWeightCache = 1024;  // weights held in LDS (k up to this many)
+
+// Upper-triangle tile t (row-major over tile rows I, J = I .. nt-1) -> (I, J).
+__device__ inline void tri_decode(int64_t t, int64_t nt, int64_t &I, int64_t &J) {
+    const double b = 2.0 * (double)nt + 1.0;
+    int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > nt - 1) r = nt - 1;
+    auto off = [nt](int64_t x) { return x * nt - x * (x - 1) / 2; };
+    while (r > 0 && off(r) > t) --r;
+    while (r + 1 < nt && off(r + 1) <= t) ++r;
+    I = r;
+    J = r + (t - off(r));
+}
+
+template <typename Acc>
+__device__ inline Acc square(float d);
+template <>
+__device__ inline float square<float>(float d) { return d * d; }
+template <>
+__device__ inline double square<double>(float d) { return (double)d * (double)d; }
+
+template <int T, int LANES, typename Acc>
+__global__ __launch_bounds__(LANES) void k_plain(
+    const float *__restrict__ mat, int64_t n, int64_t nt, int64_t n_tiles,
+    int64_t tiles_per_chunk, int64_t pgroups, int64_t grid_real,
+    const uint16_t *__restrict__ lab, int64_t P_pad, const double *__restrict__ w, int32_t k,
+    double *__restrict__ partial) {
+    // Blocks are dealt to the 8 XCDs round-robin; map them so that consecutive
+    // logical blocks (the permutation groups of one tile chunk) share an XCD
+    // and therefore its L2.
+    const int64_t gpad = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
+    if (logical >= grid_real) return;
+    const int64_t pg = logical % pgroups;
+    const int64_t chunk = logical / pgroups;
+    const int tid = threadIdx.x;
+    const int64_t perm = pg * LANES + tid;
+
+    __shared__ Acc sD[T][T];
+    __shared__ double sWt[kWeightCache];
+    const int kc = k < kWeightCache ? k : kWeightCache;
+    for (int g = tid; g < kc; g += LANES) sWt[g] = w[g];
+
+    const int64_t t0 = chunk * tiles_per_chunk;
+    int64_t t1 = t0 + tiles_per_chunk;
+    if (t1 > n_tiles) t1 = n_tiles;
+    double tot = 0.0;
+    if (t0 < t1) {
+        int64_t I, J;
+        tri_decode(t0, nt, I, J);
+        constexpr int kPer = T * T / LANES;  // staged elements per thread
+        static_assert(kPer >= 1 && (T * T) % LANES == 0, "tile/lane shape");
+        float pre[kPer];
+        // Prefetch the first tile.
+        auto fetch = [&](int64_t I_, int64_t J_) {
+            const int64_t i0 = I_ * T, j0 = J_ * T;
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const int e = tid + q * LANES;
+                const int r = e / T, c = e % T;
+                const int64_t i = i0 + r, j = j0 + c;
+                float v = 0.0f;
+                if (i < n && j < n && (I_ < J_ || c > r)) v = mat[(uint64_t)i * (uint64_t)n + j];
+                pre[q] = v;
+            }
+        };
+        fetch(I, J);
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t i0 = I * T, j0 = J * T;
+            __syncthreads();  // previous tile fully consumed (and weights written)
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const int e = tid + q * LANES;
+                sD[e / T][e % T] = square<Acc>(pre[q]);
+            }
+            uint32_t Lc[T];
+#pragma unroll
+            for (int c = 0; c < T; c++) Lc[c] = lab[(j0 + c) * P_pad + perm];
+            __syncthreads();
+            // Next tile's global loads overlap this tile's arithmetic.
+            int64_t In = I, Jn = J + 1;
+            if (Jn == nt) { In = I + 1; Jn = In; }
+            if (t + 1 < t1) fetch(In, Jn);
+#pragma unroll 2
+            for (int r = 0; r < T; r++) {
+                const uint32_t li = lab[(i0 + r) * P_pad + perm];
+                Acc acc = Acc(0);
+#pragma unroll
+                for (int c = 0; c < T; c++) acc += (li == Lc[c]) ? sD[r][c] : Acc(0);
+                double wv = 0.0;
+                if ((int32_t)li < k) wv = ((int32_t)li < kWeightCache) ? sWt[li] : w[li];
+                tot += (double)acc * wv;
+            }
+            I = In;
+            J = Jn;
+        }
+    }
+    partial[chunk * P_pad + perm] = tot;
+}
+
+template <int T, int LANES, typename Acc>
+void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t *lab,
+                const double *w, int32_t k, double *partial, hipStream_t s) {
+    const int64_t grid_real = pl.chunks * pl.pgroups;
+    const int64_t gpad = round_up(grid_real, 8);
+    hipLaunchKernelGGL((k_plain<T, LANES, Acc>), dim3((unsigned)gpad), dim3(LANES), 0, s, mat,
+                       n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups, grid_real, lab,
+                       pl.P_pad, w, k, partial);
+}
+
+} // namespace
+
+PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu, int64_t plan_P) {
+    PlainPlan pl{};
+    pl.tile = tile;
+    pl.lanes = lanes;
+    pl.n_t = ceil_div(n, tile);
+    pl.n_pad = pl.n_t * tile;
+    pl.n_tiles = tri_count(pl.n_t);
+    pl.P_pad = round_up(P > 0 ? P : 1, lanes);
+    pl.pgroups = pl.P_pad / lanes;
+    // Enough work-groups to fill every CU several times over.
+    const int64_t target = (int64_t)(n_cu > 0 ? n_cu : 256) * 32;
+    const int64_t plan_groups = plan_P > P ? ceil_div(plan_P, lanes) : pl.pgroups;
+    int64_t chunks = ceil_div(target, plan_groups);
+    if (chunks > pl.n_tiles) chunks = pl.n_tiles;
+    if (chunks < 1) chunks = 1;
+    pl.tiles_per_chunk = ceil_div(pl.n_tiles, chunks);
+    pl.chunks = ceil_div(pl.n_tiles, pl.tiles_per_chunk);
+    return pl;
+}
+
+int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
+                 const uint16_t *lab_om, const double *w, int32_t k, double *partial,
+                 hipStream_t s) {
+#define PSTAT_PLAIN_CASE(T_, L_)                                                         \
+    if (pl.tile == T_ && pl.lanes == L_) {                                               \
+        if (f64) launch_one<T_, L_, double>(pl, mat, n, lab_om, w, k, partial, s);       \
+        else launch_one<T_, L_, float>(pl, mat, n, lab_om, w, k, partial, s);            \
+        return 0;                                                                        \
+    }
+    PSTAT_PLAIN_CASE(32, 64)
+    PSTAT_PLAIN_CASE(32, 128)
+    PSTAT_PLAIN_CASE(32, 256)
+    PSTAT_PLAIN_CASE(64, 64)
+    PSTAT_PLAIN_CASE(64, 128)
+    PSTAT_PLAIN_CASE(64, 256)
+#undef PSTAT_PLAIN_CASE
+    return -1;
+}
+
+} // namespace pstat

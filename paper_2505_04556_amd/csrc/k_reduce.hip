@@ -1,0 +1,163 @@
+// FP64 reductions of per-block partials, and the statistic's last steps:
+// F, the permutation p-value and the tie band of the p-value recheck.
+#include <math.h>
+
+#include "internal.h"
+
+namespace pstat {
+
+namespace {
+
+inline unsigned blocks_for(int64_t count, int block) {
+    int64_t g = ceil_div(count, block);
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (unsigned)g;
+}
+
+// out[p] = sum over chunks, ascending, of partial[chunk][p].
+__global__ void k_reduce_plain(const double *__restrict__ partial, int64_t chunks, int64_t P_pad,
+                               int64_t P, const uint8_t *__restrict__ bad_perm,
+                               double *__restrict__ out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t c = 0; c < chunks; c++) s += partial[c * P_pad + p];
+        out[p] = (bad_perm && bad_perm[p]) ? NAN : s;
+    }
+}
+
+// tmp[p][g] = sum over items, ascending, of z[item][p][g] (FP32 -> FP64).
+__global__ void k_reduce_items(const float *__restrict__ z, int64_t items, int64_t P,
+                               int32_t k, double *__restrict__ tmp) {
+    const int64_t total = P * k;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t it = 0; it < items; it++) s += (double)z[it * total + e];
+        tmp[e] = s;
+    }
+}
+
+// out[p] = sum over g ascending of w[g] * tmp[p][g].
+__global__ void k_weight_groups(const double *__restrict__ tmp, int64_t P, int32_t k,
+                                const double *__restrict__ w,
+                                const uint8_t *__restrict__ bad_perm, double *__restrict__ out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int32_t g = 0; g < k; g++) s += w[g] * tmp[p * k + g];
+        out[p] = (bad_perm && bad_perm[p]) ? NAN : s;
+    }
+}
+
+__device__ inline double pseudo_F(double sW, double sT, int64_t n, int32_t k) {
+    if (k < 2 || n <= k) return NAN;
+    return ((sT - sW) / (double)(k - 1)) / (sW / (double)(n - k));
+}
+
+__global__ void k_F(const double *__restrict__ sW, int64_t count, const double *__restrict__ sT,
+                    int64_t n, int32_t k, double *__restrict__ F) {
+    const double t = *sT;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        F[i] = pseudo_F(sW[i], t, n, k);
+}
+
+// One block: count s_W_perm[q] <= s_W_obs (NaN compares false).
+__global__ __launch_bounds__(1024) void k_pvalue(const double *__restrict__ obs,
+                                                 const double *__restrict__ perm, int64_t P,
+                                                 double *__restrict__ p) {
+    const double o = *obs;
+    unsigned long long c = 0;
+    for (int64_t q = threadIdx.x; q < P; q += 1024) c += (perm[q] <= o) ? 1ull : 0ull;
+    __shared__ unsigned long long red[1024];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *p = P > 0 ? (double)(1 + red[0]) / (double)(1 + P) : NAN;
+}
+
+__global__ void k_flag_ties(const double *__restrict__ sW_all, int64_t P, double band,
+                            int32_t *__restrict__ list, int32_t *__restrict__ count) {
+    const double o = sW_all[0];
+    const double tol = band * fabs(o);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double v = sW_all[1 + q];
+        if (fabs(v - o) <= tol) {
+            const int32_t at = atomicAdd(count, 1);
+            list[at] = (int32_t)(1 + q);
+        }
+    }
+}
+
+__global__ void k_scatter(const double *__restrict__ vals, const int32_t *__restrict__ list,
+                          int64_t m, double *__restrict__ sW_all) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        sW_all[list[i]] = vals[i];
+}
+
+__global__ void k_pack_result(const double *__restrict__ sW_all, const double *__restrict__ sT,
+                              int64_t n, int32_t k, const double *__restrict__ p,
+                              double *__restrict__ result) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        result[0] = pseudo_F(sW_all[0], *sT, n, k);
+        result[1] = *p;
+        result[2] = sW_all[0];
+        result[3] = *sT;
+    }
+}
+
+} // namespace
+
+void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, int64_t P,
+                         const uint8_t *bad_perm, double *out, hipStream_t s) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_reduce_plain, dim3(blocks_for(P, 256)), dim3(256), 0, s, partial, chunks,
+                       P_pad, P, bad_perm, out);
+}
+
+void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
+                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_reduce_items, dim3(blocks_for(P * k, 256)), dim3(256), 0, s, z, items,
+                       P, k, tmp);
+    hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
+                       bad_perm, out);
+}
+
+void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,
+              double *F, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_F, dim3(blocks_for(count, 256)), dim3(256), 0, s, sW, count, sT, n, k, F);
+}
+
+void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_pvalue, dim3(1), dim3(1024), 0, s, sW_obs, sW_perm, P, p);
+}
+
+void launch_flag_ties(const double *sW_all, int64_t P, double band, int32_t *list,
+                      int32_t *count, hipStream_t s) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_flag_ties, dim3(blocks_for(P, 256)), dim3(256), 0, s, sW_all, P, band,
+                       list, count);
+}
+
+void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *sW_all,
+                    hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(m, 256)), dim3(256), 0, s, vals, list, m, sW_all);
+}
+
+void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32_t k,
+                        const double *p, double *result, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_result, dim3(1), dim3(64), 0, s, sW_all, sT, n, k, p, result);
+}
+
+} // namespace pstat

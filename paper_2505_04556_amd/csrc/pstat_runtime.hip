@@ -1,0 +1,670 @@
+// C ABI of libpstat.so (include/pstat.h): argument checks, per-thread context,
+// workspace carving, path dispatch and the whole-test driver.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/pstat.h"
+#include "internal.h"
+
+using namespace pstat;
+
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+
+struct Tuning {
+    int tile = 0;
+    int batch = 0;
+};
+
+struct DeviceInfo {
+    bool ready = false;
+    int n_cu = 256;
+    size_t lds_limit = 65536;
+};
+
+struct Thread {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int path = PSTAT_PATH_AUTO;
+    Tuning tuning[PSTAT_N_PATHS];
+    void *ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    // library-managed workspace (per thread, per device in use)
+    void *ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    int ws_own_device = -1;
+    // small device scalars: [0] label error flag (sticky for pstat_sW_k),
+    // [1] max label, [2] tie count
+    int32_t *flags = nullptr;
+    int flags_device = -1;
+    int32_t *host_flags = nullptr;  // pinned
+    char err[512] = {0};
+};
+
+thread_local Thread tls;
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_devices;
+
+struct Registered {
+    const float *mat;
+    int64_t n;
+    int path;
+    int device;
+    void *tiles;
+};
+std::map<int64_t, Registered> g_registered;
+int64_t g_next_handle = 1;
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(tls.err, sizeof(tls.err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    (void)hipGetLastError();
+    return fail(PSTAT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+    } while (0)
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PSTAT_EHIP, "%s launch: %s", what, hipGetErrorString(e));
+    return PSTAT_OK;
+}
+
+int need_init() {
+    if (tls.device < 0) return fail(PSTAT_ESTATE, "pstat_init has not been called on this thread");
+    return PSTAT_OK;
+}
+
+const DeviceInfo &dev_info() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_devices[tls.device];
+}
+
+// A device pointer: hipMalloc'd or managed memory.
+int check_dev_ptr(const void *p, const char *name) {
+    if (!p) return fail(PSTAT_EINVAL, "%s is NULL", name);
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PSTAT_EPTR, "%s is not device memory", name);
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(PSTAT_EPTR, "%s is not device memory (memory type %d)", name, (int)a.type);
+    return PSTAT_OK;
+}
+
+// ---- workspace carving --------------------------------------------------------
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    bool dry;  // size-only pass
+    void *take(size_t bytes) {
+        used = (used + 255) & ~(size_t)255;
+        void *p = dry ? nullptr : base + used;
+        used += bytes;
+        return p;
+    }
+};
+
+int acquire_workspace(size_t bytes, char **out) {
+    if (tls.ws_user) {
+        if (tls.ws_user_bytes < bytes)
+            return fail(PSTAT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed",
+                        tls.ws_user_bytes, bytes);
+        *out = (char *)tls.ws_user;
+        return PSTAT_OK;
+    }
+    if (tls.ws_own && tls.ws_own_device == tls.device && tls.ws_own_bytes >= bytes) {
+        *out = (char *)tls.ws_own;
+        return PSTAT_OK;
+    }
+    if (tls.ws_own) {
+        // The previous owner may still be in use by queued work on this stream.
+        HIP_TRY(hipStreamSynchronize(tls.stream));
+        (void)hipFree(tls.ws_own);
+        tls.ws_own = nullptr;
+        tls.ws_own_bytes = 0;
+    }
+    size_t grow = bytes + bytes / 4 + (1 << 20);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, grow);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&p, bytes);
+        grow = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PSTAT_ENOMEM, "could not allocate %zu bytes of device workspace", bytes);
+    }
+    tls.ws_own = p;
+    tls.ws_own_bytes = grow;
+    tls.ws_own_device = tls.device;
+    *out = (char *)p;
+    return PSTAT_OK;
+}
+
+bool is_mfma(int path) {
+    return path == PSTAT_PATH_MFMA_BF16 || path == PSTAT_PATH_MFMA_F16 ||
+           path == PSTAT_PATH_MFMA_SPLIT_BF16;
+}
+int mfma_dtype(int path) {
+    return path == PSTAT_PATH_MFMA_BF16 ? 0 : path == PSTAT_PATH_MFMA_F16 ? 1 : 2;
+}
+
+// The tuned default path and parameters for a shape (the autotuner's table is
+// applied by the Python layer through pstat_set_path / pstat_set_tuning).
+int resolve_path(int path) {
+    if (path != PSTAT_PATH_AUTO) return path;
+    return PSTAT_PATH_PLAIN_F32;
+}
+
+void plain_params(int path, int *tile, int *lanes) {
+    const Tuning &t = tls.tuning[path];
+    *tile = t.tile ? t.tile : 32;
+    *lanes = t.batch ? t.batch : 256;
+    if (path == PSTAT_PATH_PLAIN_F64 && *tile > 32) *tile = 32;
+}
+
+void mfma_params(int path, int *kchunk_cols, int *ncols) {
+    const Tuning &t = tls.tuning[path];
+    *kchunk_cols = t.tile;   // 0 = planner's choice
+    *ncols = t.batch ? t.batch : 256;
+}
+
+// ---- s_W on a staged problem ------------------------------------------------
+// Scratch of one s_W evaluation of P permutations on the given path.
+struct SwLayout {
+    int path = 0;
+    uint8_t *bad = nullptr;      // per-permutation "had a bad label" flags
+    uint16_t *lab = nullptr;     // staged labels
+    double *partial = nullptr;   // plain: [chunks][P_pad]
+    void *tiles = nullptr;       // MFMA: pre-squared tiles (unless registered)
+    int32_t *tab = nullptr;      // MFMA: work-item table
+    float *z = nullptr;          // MFMA: [items][P][k]
+    double *tmp = nullptr;       // MFMA: [P][k]
+    PlainPlan pp{};
+    MfmaPlan mp{};
+};
+
+void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
+               SwLayout &L, int64_t plan_P = 0) {
+    L.path = path;
+    L.bad = (uint8_t *)c.take((size_t)(P > 0 ? P : 1));
+    if (!is_mfma(path)) {
+        int tile, lanes;
+        plain_params(path, &tile, &lanes);
+        L.pp = plain_plan(n, P, tile, lanes, dev_info().n_cu, plan_P);
+        L.lab = (uint16_t *)c.take((size_t)L.pp.n_pad * L.pp.P_pad * sizeof(uint16_t));
+        L.partial = (double *)c.take((size_t)L.pp.chunks * L.pp.P_pad * sizeof(double));
+        return;
+    }
+    int kchunk_cols, ncols;
+    mfma_params(path, &kchunk_cols, &ncols);
+    L.mp = mfma_plan(n, P, k, mfma_dtype(path), kchunk_cols, ncols, dev_info().n_cu);
+    L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
+    if (own_tiles) L.tiles = c.take(mfma_tile_bytes(n, mfma_dtype(path)));
+    L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
+    L.z = (float *)c.take((size_t)L.mp.items * (P > 0 ? P : 1) * k * sizeof(float));
+    L.tmp = (double *)c.take((size_t)(P > 0 ? P : 1) * k * sizeof(double));
+}
+
+size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
+    Carver c{nullptr, 0, 0, true};
+    SwLayout L;
+    layout_sW(c, n, P, k, path, own_tiles, L);
+    return c.used + 256;
+}
+
+// Runs one evaluation: stage labels (row q of the staged problem is row
+// rows[q] of g, or row q when rows is NULL; rows is only used by plain paths),
+// run the kernel, reduce into out[0..P).  tiles: pre-squared tiles of a
+// registered matrix, or NULL to run the pre-pass into L.tiles.
+int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
+            const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
+            double *out, const void *tiles, int32_t *err_flag) {
+    hipStream_t s = tls.stream;
+    int32_t *maxl = tls.flags + 1;
+    int rc;
+    launch_fill_u8(L.bad, P, 0, s);
+    launch_fill_i32(maxl, 1, -1, s);
+    if (!is_mfma(L.path)) {
+        launch_stage_labels_om(g, rows, n, P, L.pp.n_pad, L.pp.P_pad, limit, L.lab, L.bad,
+                               err_flag, maxl, s);
+        if ((rc = check_launch("label staging"))) return rc;
+        if (launch_plain(L.pp, L.path == PSTAT_PATH_PLAIN_F64, mat, n, L.lab, w, k, L.partial, s))
+            return fail(PSTAT_EINVAL, "no plain kernel for tile %d, lanes %d", L.pp.tile,
+                        L.pp.lanes);
+        if ((rc = check_launch("plain s_W"))) return rc;
+        launch_reduce_plain(L.partial, L.pp.chunks, L.pp.P_pad, P, L.bad, out, s);
+        return check_launch("plain reduce");
+    }
+    if (rows) return fail(PSTAT_EINVAL, "row lists are only supported on the plain paths");
+    launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, maxl, s);
+    if ((rc = check_launch("label staging"))) return rc;
+    if (!tiles) {
+        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s);
+        if ((rc = check_launch("mfma prepass"))) return rc;
+        tiles = L.tiles;
+    }
+    if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s))
+        return fail(PSTAT_EINVAL, "no MFMA kernel for %d columns", L.mp.ncols);
+    if ((rc = check_launch("mfma s_W"))) return rc;
+    launch_reduce_mfma(L.z, L.mp.items, P, k, w, L.bad, L.tmp, out, s);
+    return check_launch("mfma reduce");
+}
+
+// Scan `count` labels against `limit`; synchronises; *max_label on success.
+int scan_labels_sync(const int32_t *g, int64_t count, int32_t limit, int32_t *max_label) {
+    hipStream_t s = tls.stream;
+    launch_fill_i32(tls.flags + 3, 1, 0, s);
+    launch_fill_i32(tls.flags + 1, 1, -1, s);
+    launch_scan_labels(g, count, limit, tls.flags + 3, tls.flags + 1, s);
+    int rc = check_launch("label scan");
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (tls.host_flags[3]) return fail(PSTAT_ELABEL, "a label is negative or >= %d", limit);
+    *max_label = tls.host_flags[1];
+    return PSTAT_OK;
+}
+
+int sW_common(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+              int32_t n_groups, const double *w, double *out, bool validate_sync,
+              const void *tiles, int path) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2 (got %lld)", (long long)n);
+    if (n_perms < 0) return fail(PSTAT_EINVAL, "n_perms must be >= 0");
+    if (!validate_sync && (n_groups < 1 || n_groups > kMaxGroups))
+        return fail(PSTAT_EINVAL, "n_groups must be in [1, %d]", kMaxGroups);
+    if (n_perms == 0) return PSTAT_OK;
+    if ((rc = check_dev_ptr(mat, "mat"))) return rc;
+    if ((rc = check_dev_ptr(groupings, "groupings"))) return rc;
+    if ((rc = check_dev_ptr(w, "inv_group_sizes"))) return rc;
+    if ((rc = check_dev_ptr(out, "out"))) return rc;
+    int32_t k = n_groups;
+    if (validate_sync) {
+        int32_t mx = -1;
+        if ((rc = scan_labels_sync(groupings, n_perms * n, kMaxGroups, &mx))) return rc;
+        k = mx + 1;
+    }
+    const size_t need = sW_bytes(n, n_perms, k, path, tiles == nullptr);
+    char *ws;
+    if ((rc = acquire_workspace(need, &ws))) return rc;
+    Carver c{ws, need, 0, false};
+    SwLayout L;
+    layout_sW(c, n, n_perms, k, path, tiles == nullptr, L);
+    return exec_sW(L, mat, n, groupings, nullptr, n_perms, k, k, w, out, tiles, tls.flags);
+}
+
+int init_flags() {
+    if (tls.flags && tls.flags_device == tls.device) return PSTAT_OK;
+    if (!tls.host_flags) HIP_TRY(hipHostMalloc((void **)&tls.host_flags, 64, hipHostMallocDefault));
+    if (tls.flags) (void)hipFree(tls.flags);
+    HIP_TRY(hipMalloc((void **)&tls.flags, 64));
+    HIP_TRY(hipMemset(tls.flags, 0, 64));
+    tls.flags_device = tls.device;
+    return PSTAT_OK;
+}
+
+double tie_band(int path) {
+    switch (path) {
+        case PSTAT_PATH_PLAIN_F32: return 1e-6;
+        case PSTAT_PATH_MFMA_SPLIT_BF16: return 2e-5;
+        case PSTAT_PATH_MFMA_F16: return 2e-3;
+        case PSTAT_PATH_MFMA_BF16: return 1e-2;
+        default: return 0.0;
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int pstat_version(void) { return kVersion; }
+
+const char *pstat_last_error(void) { return tls.err; }
+
+int pstat_init(int device) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        return fail(PSTAT_EHIP, "no HIP device available");
+    }
+    if (device < 0 || device >= count) return fail(PSTAT_EINVAL, "device %d out of range", device);
+    HIP_TRY(hipSetDevice(device));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DeviceInfo &d = g_devices[device];
+        if (!d.ready) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) ==
+                    hipSuccess && v > 0)
+                d.n_cu = v;
+            v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+                    hipSuccess && v > 0)
+                d.lds_limit = (size_t)v;
+            d.ready = true;
+        }
+    }
+    tls.device = device;
+    tls.err[0] = 0;
+    return init_flags();
+}
+
+int pstat_set_stream(void *hip_stream) {
+    tls.stream = (hipStream_t)hip_stream;
+    return PSTAT_OK;
+}
+
+int pstat_set_path(int path) {
+    if (path != PSTAT_PATH_AUTO && (path < 0 || path >= PSTAT_N_PATHS))
+        return fail(PSTAT_EINVAL, "unknown path %d", path);
+    tls.path = path;
+    return PSTAT_OK;
+}
+
+int pstat_set_tuning(int path, int tile, int batch) {
+    if (path < 0 || path >= PSTAT_N_PATHS) return fail(PSTAT_EINVAL, "unknown path %d", path);
+    if (is_mfma(path)) {
+        if (tile < 0 || tile % 64) return fail(PSTAT_EINVAL, "K chunk must be a multiple of 64");
+        if (batch != 0 && batch != 128 && batch != 256)
+            return fail(PSTAT_EINVAL, "MFMA N columns must be 128 or 256");
+    } else {
+        if (tile != 0 && tile != 32 && tile != 64) return fail(PSTAT_EINVAL, "tile must be 32 or 64");
+        if (path == PSTAT_PATH_PLAIN_F64 && tile == 64)
+            return fail(PSTAT_EINVAL, "the FP64 plain kernel uses tile 32");
+        if (batch != 0 && batch != 64 && batch != 128 && batch != 256)
+            return fail(PSTAT_EINVAL, "lanes must be 64, 128 or 256");
+    }
+    tls.tuning[path].tile = tile;
+    tls.tuning[path].batch = batch;
+    return PSTAT_OK;
+}
+
+int pstat_set_workspace(void *dev_ptr, size_t bytes) {
+    if (dev_ptr) {
+        int rc = need_init();
+        if (rc) return rc;
+        if ((rc = check_dev_ptr(dev_ptr, "workspace"))) return rc;
+    }
+    tls.ws_user = dev_ptr;
+    tls.ws_user_bytes = dev_ptr ? bytes : 0;
+    return PSTAT_OK;
+}
+
+size_t pstat_workspace_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int path) {
+    if (n < 2 || n_perms < 0 || n_groups < 1 || n_groups > kMaxGroups) return 0;
+    if (path != PSTAT_PATH_AUTO && (path < 0 || path >= PSTAT_N_PATHS)) return 0;
+    if (tls.device < 0) return 0;
+    return sW_bytes(n, n_perms, n_groups, resolve_path(path), true);
+}
+
+int pstat_sW(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+             const double *inv_group_sizes, double *out) {
+    return sW_common(mat, n, groupings, n_perms, 0, inv_group_sizes, out, true, nullptr,
+                     resolve_path(tls.path));
+}
+
+int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+               int32_t n_groups, const double *inv_group_sizes, double *out) {
+    return sW_common(mat, n, groupings, n_perms, n_groups, inv_group_sizes, out, false, nullptr,
+                     resolve_path(tls.path));
+}
+
+int pstat_check_labels(void) {
+    int rc = need_init();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           tls.stream));
+    HIP_TRY(hipStreamSynchronize(tls.stream));
+    if (tls.host_flags[0]) {
+        launch_fill_i32(tls.flags, 1, 0, tls.stream);
+        HIP_TRY(hipStreamSynchronize(tls.stream));
+        return fail(PSTAT_ELABEL, "an out-of-range label was seen");
+    }
+    return PSTAT_OK;
+}
+
+int pstat_sT(const float *mat, int64_t n, double *s_T) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2");
+    if ((rc = check_dev_ptr(mat, "mat")) || (rc = check_dev_ptr(s_T, "s_T"))) return rc;
+    char *ws;
+    const size_t need = (size_t)sT_partials_count(n) * sizeof(double) + 256;
+    if ((rc = acquire_workspace(need, &ws))) return rc;
+    launch_sT(mat, n, (double *)ws, s_T, tls.stream);
+    return check_launch("s_T");
+}
+
+int pstat_F(const double *s_W, int64_t count, const double *s_T, int64_t n, int32_t k,
+            double *F) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (k < 2 || n <= k) return fail(PSTAT_EDOMAIN, "F needs k >= 2 and n > k (k=%d, n=%lld)", k,
+                                     (long long)n);
+    if (count < 0) return fail(PSTAT_EINVAL, "count must be >= 0");
+    if (count == 0) return PSTAT_OK;
+    if ((rc = check_dev_ptr(s_W, "s_W")) || (rc = check_dev_ptr(s_T, "s_T")) ||
+        (rc = check_dev_ptr(F, "F")))
+        return rc;
+    launch_F(s_W, count, s_T, n, k, F, tls.stream);
+    return check_launch("F");
+}
+
+int pstat_pvalue(const double *s_W_obs, const double *s_W_perm, int64_t n_perms, double *p) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n_perms < 0) return fail(PSTAT_EINVAL, "n_perms must be >= 0");
+    if ((rc = check_dev_ptr(s_W_obs, "s_W_obs")) || (rc = check_dev_ptr(p, "p"))) return rc;
+    if (n_perms > 0 && (rc = check_dev_ptr(s_W_perm, "s_W_perm"))) return rc;
+    launch_pvalue(s_W_obs, s_W_perm, n_perms, p, tls.stream);
+    return check_launch("p-value");
+}
+
+int pstat_group_weights(const int32_t *grouping, int64_t n, int32_t n_groups, double *inv) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 1 || n_groups < 1 || n_groups > kMaxGroups)
+        return fail(PSTAT_EINVAL, "need n >= 1 and 1 <= n_groups <= %d", kMaxGroups);
+    if ((rc = check_dev_ptr(grouping, "grouping")) || (rc = check_dev_ptr(inv, "inv"))) return rc;
+    char *ws;
+    if ((rc = acquire_workspace((size_t)n_groups * 4 + 256, &ws))) return rc;
+    launch_group_weights(grouping, n, n_groups, (uint32_t *)ws, inv, tls.stream);
+    return check_launch("group weights");
+}
+
+int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed,
+                  int32_t *groupings) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 1 || n_perms < 0) return fail(PSTAT_EINVAL, "need n >= 1 and n_perms >= 0");
+    if (n > 0xFFFFFFFFll) return fail(PSTAT_EINVAL, "n must be < 2^32");
+    if (n_perms == 0) return PSTAT_OK;
+    if ((rc = check_dev_ptr(base, "base")) || (rc = check_dev_ptr(groupings, "groupings")))
+        return rc;
+    int32_t max_label = -1;
+    if ((rc = scan_labels_sync(base, n, kMaxGroups, &max_label))) return rc;
+    launch_permute(base, n, n_perms, seed, max_label, groupings, dev_info().lds_limit,
+                   tls.stream);
+    return check_launch("permute");
+}
+
+int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_t n_groups,
+                    int64_t n_perms, uint64_t seed, double *result, double *sW_all,
+                    int64_t *n_rechecked) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 2 || n_perms < 0) return fail(PSTAT_EINVAL, "need n >= 2 and n_perms >= 0");
+    if (n > 0xFFFFFFFFll) return fail(PSTAT_EINVAL, "n must be < 2^32");
+    if (n_groups < 2 || n <= n_groups || n_groups > kMaxGroups)
+        return fail(PSTAT_EDOMAIN, "F needs 2 <= n_groups < n (n_groups=%d)", n_groups);
+    if ((rc = check_dev_ptr(mat, "mat")) || (rc = check_dev_ptr(grouping, "grouping")) ||
+        (rc = check_dev_ptr(result, "result")))
+        return rc;
+    if (sW_all && (rc = check_dev_ptr(sW_all, "sW_all"))) return rc;
+    const int path = resolve_path(tls.path);
+    const int32_t k = n_groups;
+    hipStream_t s = tls.stream;
+    int32_t max_label = -1;
+    if ((rc = scan_labels_sync(grouping, n, k, &max_label))) return rc;
+
+    const int64_t R = n_perms + 1;  // the observed grouping is row 0
+    const int64_t nsT = sT_partials_count(n);
+    // Head block (lives through the call), then region B, reused by the main
+    // evaluation and by the FP64 recheck.
+    auto carve_head = [&](Carver &c, int32_t *&allg, double *&w, uint32_t *&counts,
+                          double *&sw, double *&sTp, double *&pv, int32_t *&list,
+                          double *&vals) {
+        allg = (int32_t *)c.take((size_t)R * n * sizeof(int32_t));
+        w = (double *)c.take((size_t)k * sizeof(double));
+        counts = (uint32_t *)c.take((size_t)k * sizeof(uint32_t));
+        sw = (double *)c.take((size_t)R * sizeof(double));
+        sTp = (double *)c.take((size_t)(nsT + 1) * sizeof(double));
+        pv = (double *)c.take(sizeof(double));
+        list = (int32_t *)c.take((size_t)R * sizeof(int32_t));
+        vals = (double *)c.take((size_t)R * sizeof(double));
+    };
+    int32_t *allg, *list;
+    double *w, *sw, *sTp, *pv, *vals;
+    uint32_t *counts;
+    Carver dry{nullptr, 0, 0, true};
+    carve_head(dry, allg, w, counts, sw, sTp, pv, list, vals);
+    const size_t head = dry.used + 256;
+    size_t region = sW_bytes(n, R, k, path, true);
+    const size_t region64 = sW_bytes(n, R, k, PSTAT_PATH_PLAIN_F64, true);
+    if (region64 > region) region = region64;
+    char *ws;
+    if ((rc = acquire_workspace(head + region, &ws))) return rc;
+    Carver hc{ws, head, 0, false};
+    carve_head(hc, allg, w, counts, sw, sTp, pv, list, vals);
+    double *sT = sTp + nsT;
+    if (sW_all) sw = sW_all;
+
+    HIP_TRY(hipMemcpyAsync(allg, grouping, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    launch_permute(grouping, n, n_perms, seed, max_label, allg + n, dev_info().lds_limit, s);
+    if ((rc = check_launch("permute"))) return rc;
+    launch_group_weights(grouping, n, k, counts, w, s);
+    if ((rc = check_launch("group weights"))) return rc;
+    {
+        Carver c{ws + head, region, 0, false};
+        SwLayout L;
+        layout_sW(c, n, R, k, path, true, L);
+        if ((rc = exec_sW(L, mat, n, allg, nullptr, R, k, k, w, sw, nullptr, tls.flags))) return rc;
+    }
+    launch_sT(mat, n, sTp, sT, s);
+    if ((rc = check_launch("s_T"))) return rc;
+
+    // Recheck in FP64: the observed grouping always (it gives F_obs), and every
+    // permutation whose s_W lies within the path's error band of the observed
+    // value, so that the p-value count is decided at FP64 accuracy.
+    int64_t rechecked = 0;
+    const double band = tie_band(path);
+    if (band > 0.0) {
+        int64_t m = 0;
+        if (n_perms > 0) {
+            launch_fill_i32(tls.flags + 2, 1, 0, s);
+            launch_flag_ties(sw, n_perms, band, list + 1, tls.flags + 2, s);
+            if ((rc = check_launch("tie flags"))) return rc;
+            HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, 3 * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            m = tls.host_flags[2];
+        }
+        const int64_t M = m + 1;
+        launch_fill_i32(list, 1, 0, s);
+        Carver c{ws + head, region, 0, false};
+        SwLayout L;
+        layout_sW(c, n, M, k, PSTAT_PATH_PLAIN_F64, true, L, R);
+        if ((rc = exec_sW(L, mat, n, allg, list, M, k, k, w, vals, nullptr, tls.flags))) return rc;
+        launch_scatter(vals, list, M, sw, s);
+        if ((rc = check_launch("recheck scatter"))) return rc;
+        rechecked = m;
+    }
+    launch_pvalue(sw, sw + 1, n_perms, pv, s);
+    launch_pack_result(sw, sT, n, k, pv, result, s);
+    if ((rc = check_launch("result"))) return rc;
+    if (n_rechecked) *n_rechecked = rechecked;
+    return PSTAT_OK;
+}
+
+int pstat_matrix_register(const float *mat, int64_t n, int path, int64_t *handle) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (!handle) return fail(PSTAT_EINVAL, "handle is NULL");
+    if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2");
+    if ((rc = check_dev_ptr(mat, "mat"))) return rc;
+    path = resolve_path(path);
+    if (path < 0 || path >= PSTAT_N_PATHS) return fail(PSTAT_EINVAL, "unknown path %d", path);
+    void *tiles = nullptr;
+    if (is_mfma(path)) {
+        HIP_TRY(hipMalloc(&tiles, mfma_tile_bytes(n, mfma_dtype(path))));
+        launch_mfma_prepass(mat, n, mfma_dtype(path), tiles, tls.stream);
+        if ((rc = check_launch("mfma prepass"))) {
+            (void)hipFree(tiles);
+            return rc;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int64_t h = g_next_handle++;
+    g_registered[h] = Registered{mat, n, path, tls.device, tiles};
+    *handle = h;
+    return PSTAT_OK;
+}
+
+int pstat_matrix_release(int64_t handle) {
+    Registered r;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_registered.find(handle);
+        if (it == g_registered.end()) return fail(PSTAT_EINVAL, "unknown handle %lld", (long long)handle);
+        r = it->second;
+        g_registered.erase(it);
+    }
+    if (r.tiles) {
+        // queued work may still read the tiles
+        HIP_TRY(hipStreamSynchronize(tls.stream));
+        HIP_TRY(hipFree(r.tiles));
+    }
+    return PSTAT_OK;
+}
+
+int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perms,
+                        int32_t n_groups, const double *inv_group_sizes, double *out) {
+    Registered r;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_registered.find(handle);
+        if (it == g_registered.end()) return fail(PSTAT_EINVAL, "unknown handle %lld", (long long)handle);
+        r = it->second;
+    }
+    if (r.device != tls.device) return fail(PSTAT_EINVAL, "handle belongs to device %d", r.device);
+    return sW_common(r.mat, r.n, groupings, n_perms, n_groups, inv_group_sizes, out, false,
+                     r.tiles, r.path);
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/pstat.h declares; the oracle and input generators are importable."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pstat.h")
+LIB = os.path.join(ROOT, "paper_2505_04556_amd", "libpstat.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pstat_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2505_04556_amd import build
+        build.build_pstat()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_papers_calls():
+    syms = declared_symbols()
+    for name in ("pstat_sW", "pstat_F", "pstat_pvalue", "pstat_permute", "pstat_sT"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_exports_match_nm():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(pstat_[A-Za-z0-9_]+)\b", out))
+    assert set(declared_symbols()) <= exported
+
+
+def test_no_device_calls_without_init(lib):
+    # Before pstat_init every compute call must refuse with PSTAT_ESTATE (-7)
+    # without touching a device.
+    lib.pstat_sW.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.pstat_sW(None, 10, None, 1, None, None) == -7
+    lib.pstat_last_error.restype = ctypes.c_char_p
+    assert b"pstat_init" in lib.pstat_last_error()
+    assert lib.pstat_version() >= 10000
+
+
+def test_binding_names_match_header():
+    import importlib
+    try:
+        mod = importlib.import_module("paper_2505_04556_amd")
+    except ImportError:
+        pytest.skip("library not built")
+    assert sorted(mod.exported_symbols()) == declared_symbols()

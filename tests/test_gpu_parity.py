@@ -1,0 +1,307 @@
+"""GPU parity: every computation form of the HIP library against the FP64 CPU
+oracle on the same seeded inputs, through the C ABI (Python binding = argument
+marshalling only).  Small and ragged sizes that span several tiles, plus the
+degenerate cases; the full workloads are in test_gpu_fullsize.py."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, load_pstat, max_rel, problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ALL_PATHS = ["plain_f32", "plain_f64", "mfma_split_bf16", "mfma_f16", "mfma_bf16"]
+
+
+@pytest.fixture(scope="module")
+def ps(dev):
+    return load_pstat()
+
+
+def run_sW(ps, path, D, perms, w, validate=True, k=None, tuning=None):
+    import torch
+    ps.pstat_set_path(path)
+    if tuning:
+        ps.pstat_set_tuning(path, *tuning)
+    Dd, gd, wd = to_dev(D, perms, w)
+    out = (ps.pstat_sW(Dd, gd, wd) if validate else ps.pstat_sW_k(Dd, gd, k, wd))
+    torch.cuda.synchronize()
+    if tuning:
+        ps.pstat_set_tuning(path, 0, 0)
+    return out.cpu().numpy()
+
+
+# --- input generators: device copy == host copy ----------------------------
+def test_device_generators_match_host(ps):
+    import synth.device as sd
+    for n in (1, 2, 77, 300):
+        a = sd.uniform_matrix(n, 1234).cpu().numpy()
+        assert np.array_equal(a, synth.uniform_matrix(n, 1234))
+    b = sd.euclid_matrix(150, 99).cpu().numpy()
+    h = synth.euclid_matrix(150, 99)
+    assert np.max(np.abs(b.astype(np.float64) - h)) <= 2.0 ** -24
+
+
+# --- permutation generator: bit-exact with the oracle's ---------------------
+@pytest.mark.parametrize("n,maxlab,P,seed", [
+    (16, 2, 4, 3000), (2, 1, 7, 1), (1000, 3, 999, 3000), (500, 300, 64, 77),
+    (90_000, 299, 3, 5),          # u16 labels that do not fit in LDS: in-place path
+    (20_000, 4, 130, 9),          # u8 labels, several permutations per work-group
+])
+def test_permute_bit_exact(ps, n, maxlab, P, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    base = np.sort(rng.integers(0, maxlab + 1, size=n)).astype(np.int32)
+    base[-1] = maxlab
+    got = ps.pstat_permute(torch.from_numpy(base).cuda(), P, seed).cpu().numpy()
+    assert np.array_equal(got, oracle.permute(base, P, seed))
+
+
+def test_permute_golden_fixture(ps):
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(__file__), "golden", "permute_n16_P4_seed3000.txt")
+    rows = [list(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    got = ps.pstat_permute(torch.tensor(rows[0], dtype=torch.int32).cuda(), 4, 3000)
+    assert got.cpu().numpy().tolist() == rows[1:]
+
+
+# --- s_W: every path, ragged sizes ---------------------------------------
+SHAPES = [(2, [2], 1), (3, [1, 2], 5), (33, [10, 23], 63), (65, [20, 20, 25], 65),
+          (100, [10, 20, 30, 40], 300), (257, [57, 100, 100], 129), (1000, [100, 200, 300, 400], 999)]
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("n,sizes,P", SHAPES)
+def test_sW_matches_oracle(ps, path, n, sizes, P):
+    D, base, perms, w = problem(n, sizes, P, mseed=n, pseed=P)
+    ref = oracle.sW(D, perms, w)
+    got = run_sW(ps, path, D, perms, w)
+    err = max_rel(got, ref)
+    assert err <= TOL[path], f"{path} n={n} P={P}: max rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("tile,lanes", [(32, 64), (32, 128), (64, 64), (64, 128), (64, 256)])
+def test_plain_tunings(ps, tile, lanes):
+    D, base, perms, w = problem(300, [50, 100, 150], 200, mseed=4, pseed=5)
+    ref = oracle.sW(D, perms, w)
+    got = run_sW(ps, "plain_f32", D, perms, w, tuning=(tile, lanes))
+    assert max_rel(got, ref) <= TOL["plain_f32"]
+
+
+@pytest.mark.parametrize("kcols", [64, 128, 512])
+def test_mfma_k_chunks(ps, kcols):
+    D, base, perms, w = problem(700, [100, 250, 350], 50, mseed=6, pseed=7)
+    ref = oracle.sW(D, perms, w)
+    got = run_sW(ps, "mfma_split_bf16", D, perms, w, tuning=(kcols, 256))
+    assert max_rel(got, ref) <= TOL["mfma_split_bf16"]
+
+
+def test_many_groups(ps):
+    # k = 40 groups: 10,240 columns of G for 256 permutations
+    sizes = [5 + (g % 7) for g in range(40)]
+    n = sum(sizes)
+    D, base, perms, w = problem(n, sizes, 256, mseed=8, pseed=9)
+    ref = oracle.sW(D, perms, w)
+    for path in ALL_PATHS:
+        assert max_rel(run_sW(ps, path, D, perms, w), ref) <= TOL[path], path
+
+
+# --- exactness and degenerate cases ---------------------------------------
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_dyadic_inputs_bit_exact(ps, path):
+    # d = m/16: d^2 exact in every input type; power-of-two group sizes make
+    # every weight exact, so every path must reproduce the oracle bit for bit
+    sizes = [16, 32, 64, 16]
+    D, base, perms, w = problem(sum(sizes), sizes, 70, mseed=3, pseed=4, matrix="dyadic")
+    ref = oracle.sW(D, perms, w)
+    got = run_sW(ps, path, D, perms, w)
+    assert np.array_equal(got, ref), f"{path}: max rel err {max_rel(got, ref):.3e}"
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_all_singletons_exact_zero(ps, path):
+    n = 64
+    D = synth.uniform_matrix(n, 3)
+    g = np.arange(n, dtype=np.int32)[None, :].repeat(3, 0)
+    got = run_sW(ps, path, D, g, np.ones(n))
+    assert np.all(got == 0.0)
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_single_group_is_frobenius(ps, path):
+    n = 190
+    D = synth.uniform_matrix(n, 12)
+    g = np.zeros((2, n), dtype=np.int32)
+    got = run_sW(ps, path, D, g, np.array([1.0 / n]))
+    fro = np.linalg.norm(D.astype(np.float64)) ** 2 / (2 * n)
+    assert max_rel(got, [fro, fro]) <= TOL[path]
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_only_strict_upper_triangle_is_read(ps, path):
+    D, base, perms, w = problem(150, [50, 100], 20, mseed=2, pseed=3)
+    E = D.copy()
+    E[np.tril_indices(150)] = np.nan
+    a = run_sW(ps, path, D, perms, w)
+    b = run_sW(ps, path, E, perms, w)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_constant_matrix_closed_form(ps, path):
+    sizes = [8, 16, 32, 8]
+    n, k = sum(sizes), 4
+    D = np.full((n, n), 0.5, dtype=np.float32)
+    np.fill_diagonal(D, 0)
+    perms = oracle.permute(synth.base_labels(sizes), 10, 1)
+    got = run_sW(ps, path, D, perms, synth.inv_group_sizes(sizes))
+    assert np.all(got == 0.25 * (n - k) / 2)
+
+
+def test_results_are_deterministic(ps):
+    D, base, perms, w = problem(500, [100, 400], 300, mseed=5, pseed=6)
+    for path in ALL_PATHS:
+        a = run_sW(ps, path, D, perms, w)
+        b = run_sW(ps, path, D, perms, w)
+        assert np.array_equal(a, b), path
+
+
+# --- boundary: error codes --------------------------------------------------
+def test_bad_labels_rejected_and_out_untouched(ps):
+    import torch
+    D, base, perms, w = problem(40, [20, 20], 5)
+    perms = perms.copy()
+    perms[3, 7] = -1
+    Dd, gd, wd = to_dev(D, perms, w)
+    out = torch.full((5,), 7.0, dtype=torch.float64, device="cuda")
+    ps.pstat_set_path("plain_f32")
+    with pytest.raises(ps.PstatError) as e:
+        ps.pstat_sW(Dd, gd, wd, out)
+    assert e.value.code == ps.PSTAT_ELABEL
+    assert torch.all(out == 7.0)
+    perms[3, 7] = 70000
+    with pytest.raises(ps.PstatError):
+        ps.pstat_sW(Dd, to_dev(perms)[0], wd, out)
+
+
+def test_async_label_check_marks_nan(ps):
+    import torch
+    D, base, perms, w = problem(40, [20, 20], 5)
+    perms = perms.copy()
+    perms[2, 0] = 2                       # >= n_groups
+    for path in ("plain_f32", "mfma_split_bf16"):
+        ps.pstat_set_path(path)
+        Dd, gd, wd = to_dev(D, perms, w)
+        out = ps.pstat_sW_k(Dd, gd, 2, wd).cpu().numpy()
+        assert np.isnan(out[2]) and np.all(np.isfinite(np.delete(out, 2)))
+        with pytest.raises(ps.PstatError) as e:
+            ps.pstat_check_labels()
+        assert e.value.code == ps.PSTAT_ELABEL
+        ps.pstat_check_labels()            # the flag was cleared
+
+
+def test_host_pointers_and_bad_sizes(ps):
+    import torch
+    ps.pstat_set_path("plain_f32")
+    lib = ps._lib
+    D, base, perms, w = problem(20, [10, 10], 2)
+    out = np.zeros(2)
+    rc = lib.pstat_sW(D.ctypes.data, 20, perms.ctypes.data, 2, w.ctypes.data, out.ctypes.data)
+    assert rc == ps.PSTAT_EPTR
+    Dd, gd, wd = to_dev(D, perms, w)
+    od = torch.zeros(2, dtype=torch.float64, device="cuda")
+    assert lib.pstat_sW(Dd.data_ptr(), 1, gd.data_ptr(), 2, wd.data_ptr(), od.data_ptr()) == ps.PSTAT_EINVAL
+    assert lib.pstat_sW(Dd.data_ptr(), 20, gd.data_ptr(), -1, wd.data_ptr(), od.data_ptr()) == ps.PSTAT_EINVAL
+    assert lib.pstat_sW(Dd.data_ptr(), 20, gd.data_ptr(), 0, wd.data_ptr(), od.data_ptr()) == ps.PSTAT_OK
+    assert lib.pstat_set_path(17) == ps.PSTAT_EINVAL
+    assert lib.pstat_set_tuning(0, 48, 0) == ps.PSTAT_EINVAL
+    assert lib.pstat_F(od.data_ptr(), 2, od.data_ptr(), 20, 1, od.data_ptr()) == ps.PSTAT_EDOMAIN
+    assert lib.pstat_F(od.data_ptr(), 2, od.data_ptr(), 20, 20, od.data_ptr()) == ps.PSTAT_EDOMAIN
+
+
+def test_user_workspace(ps):
+    import torch
+    D, base, perms, w = problem(300, [100, 200], 100)
+    ref = oracle.sW(D, perms, w)
+    for path in ("plain_f32", "mfma_split_bf16"):
+        ps.pstat_set_path(path)
+        need = ps.pstat_workspace_bytes(300, 100, 2, path)
+        assert need > 0
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        ps.pstat_set_workspace(ws)
+        try:
+            Dd, gd, wd = to_dev(D, perms, w)
+            got = ps.pstat_sW_k(Dd, gd, 2, wd).cpu().numpy()
+            assert max_rel(got, ref) <= TOL[path]
+            ps.pstat_set_workspace(ws[: need // 4])
+            with pytest.raises(ps.PstatError) as e:
+                ps.pstat_sW_k(Dd, gd, 2, wd)
+            assert e.value.code == ps.PSTAT_ENOMEM
+        finally:
+            ps.pstat_set_workspace(None)
+
+
+def test_registered_matrix(ps):
+    D, base, perms, w = problem(400, [150, 250], 64)
+    Dd, gd, wd = to_dev(D, perms, w)
+    for path in ("plain_f32", "mfma_split_bf16", "mfma_bf16"):
+        ps.pstat_set_path(path)
+        direct = ps.pstat_sW_k(Dd, gd, 2, wd).cpu().numpy()
+        h = ps.pstat_matrix_register(Dd, path)
+        try:
+            a = ps.pstat_sW_registered(h, gd, 2, wd).cpu().numpy()
+            b = ps.pstat_sW_registered(h, gd, 2, wd).cpu().numpy()
+        finally:
+            ps.pstat_matrix_release(h)
+        assert np.array_equal(a, direct) and np.array_equal(b, direct)
+
+
+# --- s_T, F, p-value and the whole test ---------------------------------------
+def test_sT_F_pvalue_kernels(ps):
+    import torch
+    D, base, perms, w = problem(500, [100, 150, 250], 199)
+    sW = oracle.sW(D, np.vstack([base, perms]), w)
+    sT = oracle.sT(D)
+    Dd, swd = to_dev(D, sW)
+    sTd = ps.pstat_sT(Dd)
+    assert max_rel(sTd.cpu().numpy(), [sT]) <= 1e-13
+    # the F kernel on the oracle's s_T (F near 0 would amplify the last-bit
+    # difference between the two s_T sums)
+    Fd = ps.pstat_F(swd, to_dev(np.array([sT]))[0], 500, 3).cpu().numpy()
+    Fo = oracle.F(sW, sT, 500, 3)
+    assert np.max(np.abs(Fd - Fo) / np.maximum(np.abs(Fo), 1.0)) <= 1e-13
+    p = ps.pstat_pvalue(swd[:1], swd[1:]).item()
+    assert p == oracle.pvalue_sW(sW[0], sW[1:])
+    empty = torch.empty(0, dtype=torch.float64, device="cuda")
+    assert np.isnan(ps.pstat_pvalue(swd[:1], empty).item())
+
+
+def test_group_weights(ps):
+    import torch
+    g = np.array([0, 2, 2, 1, 2, 0, 4], dtype=np.int32)
+    got = ps.pstat_group_weights(torch.from_numpy(g).cuda(), 5).cpu().numpy()
+    assert np.array_equal(got, [0.5, 1.0, 1 / 3, 0.0, 1.0])
+
+
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_bf16"])
+def test_permanova_matches_oracle(ps, path):
+    import torch
+    cfg = synth.config(0)
+    D = synth.host_matrix(cfg)
+    base = synth.base_labels(cfg["sizes"])
+    P, seed = cfg["n_perms"], cfg["perm_seed"]
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, cfg["k"], P, seed, sW_all=sw)
+    res = res.cpu().numpy()
+    sw = sw.cpu().numpy()
+    assert max_rel(sw[1:], ref["sW_perm"]) <= TOL[path]
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+    assert res[1] == ref["p"], (res[1], ref["p"], rechecked)
+    assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
