@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: the whole PERMANOVA permutation test on one MI355X.
+
+One step = one ``pstat_permanova`` call on a matrix already resident in HBM:
+Fisher-Yates generation of every permutation, label staging, the s_W kernel
+(plain or MFMA form, plus the MFMA pre-pass), the FP64 reductions, s_T, the FP64
+recheck of the observed grouping and of near-tie permutations, F and the
+p-value.  Workload: n = 10,000 Euclidean distances between seeded N(0, 1)
+points in 32 dimensions scaled to [0, 1], k = 5 groups of 1000/1500/2000/2500/
+3000, 9,999 permutations (a synthetic stand-in for the paper's UniFrac data).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+
+Prints one JSON line.  ``value`` is pair-permutations per second of the
+fastest form that meets the 1e-5 relative accuracy bar (plain FP32 or split
+BF16 MFMA); both forms are timed and reported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak figures of one MI355X used as roofline denominators.
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+# Plain VALU kernel: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz single (non-packed)
+# lane operations per second; the kernel spends 3 per pair-permutation.
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PLAIN_OPS_PER_PAIRPERM = 3
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load():
+    lib = os.path.join(ROOT, "paper_2505_04556_amd", "libpstat.so")
+    if not os.path.exists(lib) or not os.path.exists(os.path.join(ROOT, "synth", "libsynth.so")):
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "pstat_build", os.path.join(ROOT, "paper_2505_04556_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build_all()
+    import paper_2505_04556_amd as ps
+    return ps
+
+
+def time_path(ps, torch, path, D, base, cfg, steps, warmup):
+    """Warm up, then time exactly `steps` whole tests; returns timings and the
+    last step's outputs."""
+    ps.pstat_set_path(path)
+    n, k, P, seed = cfg["n"], cfg["k"], cfg["n_perms"], cfg["perm_seed"]
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res = torch.empty(4, dtype=torch.float64, device="cuda")
+    rechecked = 0
+    for _ in range(warmup):
+        _, rechecked = ps.pstat_permanova(D, base, k, P, seed, result=res, sW_all=sw)
+    torch.cuda.synchronize()
+    ps.pstat_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, rechecked = ps.pstat_permanova(D, base, k, P, seed, result=res, sW_all=sw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, launches = ps.pstat_profile_read()
+    ps.pstat_profile(False)
+    return dict(path=path, seconds=dt, ms_per_step=dt * 1e3 / steps, kernel_ms_total=kms,
+                kernel_launches=launches, rechecked=rechecked, sW=sw.cpu().numpy(),
+                result=res.cpu().numpy())
+
+
+def cpu_baseline(D_host, cfg, target_s=12.0):
+    """The FP64 oracle, as it stands, on this host's cores over a bounded
+    sample of the same workload's permutations."""
+    import numpy as np
+    import oracle
+    import synth
+    n = cfg["n"]
+    base = synth.base_labels(cfg["sizes"])
+    w = synth.inv_group_sizes(cfg["sizes"])
+    threads = oracle.max_threads()
+    pairs = n * (n - 1) / 2
+    m = max(2, threads)
+    perms = oracle.permute(base, m, cfg["perm_seed"])
+    t0 = time.perf_counter()
+    ref = oracle.sW(D_host, perms, w)
+    dt = time.perf_counter() - t0
+    rate = m * pairs / dt
+    m2 = int(min(cfg["n_perms"], max(m, target_s * rate / pairs)))
+    m2 = max(threads, (m2 // threads) * threads)
+    if m2 > m:
+        perms = oracle.permute(base, m2, cfg["perm_seed"])
+        t0 = time.perf_counter()
+        ref = oracle.sW(D_host, perms, w)
+        dt = time.perf_counter() - t0
+        m = m2
+    return dict(value=m * pairs / dt / 1e9, seconds=dt, perms=m, threads=threads, sW=ref,
+                perms_array=perms)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--paths", default="plain_f32,mfma_split_bf16")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the permutation "
+              "axis would shard across GPUs, but this build measures one GPU's share.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import synth.device as sd
+
+    ps = load()
+    cfg = synth.config(args.config)
+    n, k, P = cfg["n"], cfg["k"], cfg["n_perms"]
+    log(f"workload {cfg['name']}: generating the matrix on the device")
+    D = sd.matrix(cfg)
+    base = torch.from_numpy(synth.base_labels(cfg["sizes"])).cuda()
+    torch.cuda.synchronize()
+    pairs = n * (n - 1) // 2
+    pair_perms = pairs * P
+
+    runs = {}
+    for path in args.paths.split(","):
+        log(f"timing {path}: {args.warmup} warm-up + {args.steps} steps")
+        runs[path] = time_path(ps, torch, path, D, base, cfg, args.steps, args.warmup)
+        log(f"  {path}: {runs[path]['ms_per_step']:.2f} ms/step, "
+            f"kernel {runs[path]['kernel_ms_total'] / max(1, runs[path]['kernel_launches']):.2f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline(D.cpu().numpy(), cfg)
+        log(f"  oracle: {cpu['value']:.3f} G pair-perms/s on {cpu['threads']} threads, "
+            f"{cpu['perms']} perms in {cpu['seconds']:.1f} s")
+
+    # Accuracy of each timed run on the oracle's sample (same generator, same seed).
+    acc = {}
+    if cpu is not None:
+        m = cpu["perms"]
+        for path, r in runs.items():
+            got = r["sW"][1:1 + m]
+            acc[path] = float(np.max(np.abs(got - cpu["sW"]) / np.abs(cpu["sW"])))
+
+    ok_paths = [p for p in runs if p in ("plain_f32", "mfma_split_bf16")]
+    best = min(ok_paths, key=lambda p: runs[p]["ms_per_step"])
+    r = runs[best]
+    value = pair_perms / (r["ms_per_step"] / 1e3) / 1e9
+    kern_ms = r["kernel_ms_total"] / max(1, r["kernel_launches"])
+    R = P + 1
+    if best.startswith("mfma"):
+        s = 2 if "split" in best else 1
+        work = 2.0 * k * s * pairs * R
+        achieved = work / (kern_ms / 1e3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
+                    kernel="k_mfma<2> (split-BF16)", kernel_ms=round(kern_ms, 4),
+                    work_per_launch=f"{2 * k * s} flop x {pairs} pairs x {R} groupings")
+    else:
+        work = PLAIN_OPS_PER_PAIRPERM * pairs * R
+        achieved = work / (kern_ms / 1e3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 2), peak=round(PEAK_VALU_TOPS, 2),
+                    unit="TFLOP/s", frac=round(achieved / PEAK_VALU_TOPS, 4), traffic=None,
+                    kernel="k_plain<32,256,float>", kernel_ms=round(kern_ms, 4),
+                    work_per_launch=f"{PLAIN_OPS_PER_PAIRPERM} VALU lane-ops x {pairs} pairs x "
+                                    f"{R} groupings")
+
+    out = {
+        "metric": "G pair-perms/s for s_W (whole permutation test), plain vs MFMA at 1e-5 rel err",
+        "value": round(value, 3),
+        "unit": "G pair-perms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 hi+lo -> f32 accumulate -> f64" if best.startswith("mfma") else "f32 -> f64",
+        "data": "synthetic (seeded Euclidean distances of N(0,1) points, 32 dims, scaled to [0,1])",
+        "config": {"workload": cfg["name"], "n": n, "k": k, "group_sizes": cfg["sizes"],
+                   "n_perms": P, "path": best},
+        "roofline": roof,
+        "paths": {p: {"ms_per_step": round(v["ms_per_step"], 4),
+                      "G_pair_perms_per_s": round(pair_perms / (v["ms_per_step"] / 1e3) / 1e9, 3),
+                      "kernel_ms": round(v["kernel_ms_total"] / max(1, v["kernel_launches"]), 4),
+                      "F_obs": float(v["result"][0]), "p": float(v["result"][1]),
+                      "rechecked_perms": int(v["rechecked"]),
+                      "max_rel_err_vs_oracle_sample": acc.get(p)}
+                  for p, v in runs.items()},
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = {"value": round(cpu["value"], 4), "unit": "G pair-perms/s",
+                               "cores": cpu["threads"], "kind": "oracle",
+                               "sample": f"FP64 oracle s_W of the first {cpu['perms']} of the "
+                                         f"{P} permutations (same matrix, same generator), "
+                                         f"{cpu['seconds']:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

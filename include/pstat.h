@@ -81,7 +81,7 @@ int pstat_set_path(int path);
  * values (0 = keep the tuned value).  Plain paths: tile = square tile edge
  * (32 or 64), batch = permutation lanes per work-group (64, 128 or 256).  MFMA
  * paths: tile = K-chunk length in columns (multiple of 64, 0 = tuned), batch =
- * N columns per work-group (128 or 256).  Invalid values give PSTAT_EINVAL. */
+ * N columns per work-group (256 or 512).  Invalid values give PSTAT_EINVAL. */
 int pstat_set_tuning(int path, int tile, int batch);
 
 /* Caller-owned device workspace for this thread (NULL, 0 = library-managed). */
@@ -163,6 +163,19 @@ int pstat_matrix_release(int64_t handle);
 /* pstat_sW_k on a registered matrix with that registration's path. */
 int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perms,
                         int32_t n_groups, const double *inv_group_sizes, double *out);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* While enabled (on != 0), every s_W evaluation on this thread records a pair
+ * of HIP events on its stream around its main kernel (the plain kernel or the
+ * MFMA kernel; not staging, pre-pass or reduction).  Enabling clears earlier
+ * records. */
+int pstat_profile(int on);
+
+/* Synchronises the recorded events and returns the summed duration of the
+ * main-kernel launches recorded since pstat_profile(1) (*ms, milliseconds)
+ * and their count (*launches); both host pointers, either may be NULL. */
+int pstat_profile_read(double *ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,7 @@ function has the C entry point's name and only marshals arguments: torch CUDA
 tensors in, device pointers and sizes out, the library's status code turned
 into an exception.  All computation runs in the library's HIP kernels; there
 is no CPU fallback, and importing this package fails loudly if the library has
-not been built (``python -m paper_2505_04556_amd.build``).
+not been built (``python paper_2505_04556_amd/build.py``).
 
 torch supplies device memory and the current stream only.
 """
@@ -57,7 +57,7 @@ class PstatError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_04556_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2505_04556_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 _P = ctypes.c_void_p
@@ -84,6 +84,8 @@ _SIGS = {
     "pstat_matrix_register": ([_P, _i64, _int, ctypes.POINTER(_i64)], _int),
     "pstat_matrix_release": ([_i64], _int),
     "pstat_sW_registered": ([_i64, _P, _i64, _i32, _P, _P], _int),
+    "pstat_profile": ([_int], _int),
+    "pstat_profile_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -274,6 +276,18 @@ def pstat_sW_registered(handle: int, groupings: torch.Tensor, n_groups: int,
                                     _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
                                     _dev(out, torch.float64, "out")))
     return out
+
+
+def pstat_profile(on: bool) -> None:
+    _check(_lib.pstat_profile(1 if on else 0))
+
+
+def pstat_profile_read() -> tuple[float, int]:
+    """(summed main-kernel milliseconds, launches) since pstat_profile(True)."""
+    ms = ctypes.c_double(0.0)
+    cnt = _i64(0)
+    _check(_lib.pstat_profile_read(ctypes.byref(ms), ctypes.byref(cnt)))
+    return float(ms.value), int(cnt.value)
 
 
 def exported_symbols() -> list[str]:

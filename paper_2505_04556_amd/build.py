@@ -1,7 +1,9 @@
 """Compiles the HIP sources of this package (and the device input generators
 of ``synth``) for gfx950 into in-tree shared libraries.
 
-    python -m paper_2505_04556_amd.build
+    python paper_2505_04556_amd/build.py
+
+(Run it as a file: importing the package itself needs the library it builds.)
 """
 from __future__ import annotations
 

@@ -22,19 +22,18 @@ inline int64_t tri_count(int64_t nt) { return nt * (nt + 1) / 2; }
 // ---- staging (k_stage.hip) ------------------------------------------------
 // int32 [.][n] -> u16 [n_pad][P_pad] (object-major), pads with kPadLabel;
 // staged permutation q is row rows[q] of g (row q when rows is NULL).
-// Labels outside [0, limit) set bad_perm[q] = 1 and *err_flag |= 1; *max_label
-// receives the largest label seen (atomicMax; the caller sets it to -1 first).
+// Labels outside [0, limit) set bad_perm[q] = 1 and *err_flag |= 1.
 void launch_stage_labels_om(const int32_t *g, const int32_t *rows, int64_t n, int64_t P,
                             int64_t n_pad, int64_t P_pad, int32_t limit, uint16_t *out,
-                            uint8_t *bad_perm, int32_t *err_flag, int32_t *max_label,
-                            hipStream_t s);
-// Range check and maximum of `count` int32 labels (no staging).
+                            uint8_t *bad_perm, int32_t *err_flag, hipStream_t s);
+// Range check and maximum of `count` int32 labels (no staging); *max_label
+// receives the largest label (atomicMax; the caller sets it to -1 first).
 void launch_scan_labels(const int32_t *g, int64_t count, int32_t limit, int32_t *err_flag,
                         int32_t *max_label, hipStream_t s);
 // int32 [P][n] -> u16 [P_pad][n_pad] (permutation-major), same checks.
 void launch_stage_labels_pm(const int32_t *g, int64_t n, int64_t P, int64_t n_pad,
                             int64_t P_pad, int32_t limit, uint16_t *out, uint8_t *bad_perm,
-                            int32_t *err_flag, int32_t *max_label, hipStream_t s);
+                            int32_t *err_flag, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_t *counts,
@@ -56,9 +55,7 @@ struct PlainPlan {
     int64_t P_pad;   // permutations rounded up to `lanes`
     int64_t n_pad;   // n rounded up to T
 };
-// plan_P (>= P, or 0 for P) sets the chunk count, so a plan for fewer
-// permutations than plan_P never needs more scratch than one for plan_P.
-PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu, int64_t plan_P = 0);
+PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu);
 // partial[chunk][P_pad] FP64 from u16 [n_pad][P_pad] labels.  Perm lane q of
 // the label table is permutation q.  f64 selects the FP64 instantiation.
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
@@ -101,10 +98,14 @@ void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int3
               double *F, hipStream_t s);
 void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,
                    hipStream_t s);
-// Flag permutations with |sW[q] - sW_obs| <= band * |sW_obs| (q in 1..P of
-// sW_all) into list (1-based indices into sW_all); *count = number flagged.
-void launch_flag_ties(const double *sW_all, int64_t P, double band, int32_t *list,
-                      int32_t *count, hipStream_t s);
+// Rows q in [q0, R) of sW_all with |sW_all[q] - sW_all[0]| <= *band * |sW_all[0]|
+// go to list (row indices); *count (zeroed by the caller) = number flagged.
+void launch_flag_ties(const double *sW_all, int64_t q0, int64_t R, const double *band,
+                      int32_t *list, int32_t *count, hipStream_t s);
+// *band = margin * max_j |fast[j] - exact[j]| / |exact[0]|, j < S, floor 1e-13.
+void launch_tie_band(const double *fast, const double *exact, int64_t S, double margin,
+                     double *band, hipStream_t s);
+void launch_iota(int32_t *list, int64_t m, hipStream_t s);
 void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *sW_all,
                     hipStream_t s);
 void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32_t k,

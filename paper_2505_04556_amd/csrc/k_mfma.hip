@@ -11,9 +11,10 @@
 // blocks.  A pre-pass writes, for each panel I, its K blocks from the diagonal
 // (block 2I) to the end, each as 128 x 64 values in MFMA fragment order, with
 // the entries j <= i of the diagonal blocks set to zero.  The main kernel
-// computes Y = U_panel * G over a K range for 256 columns (p, g) of G at a time
-// with v_mfma_f32_32x32x16_{bf16,f16} (FP32 accumulation), building the
-// one-hot B fragments in registers from u16 labels, and in its epilogue keeps
+// computes Y = U_panel * G over a K range for 256 or 512 columns (p, g) of G at
+// a time with v_mfma_f32_32x32x16_{bf16,f16} (FP32 accumulation), staging the
+// K blocks of U in LDS and building the one-hot B fragments in registers from
+// u16 labels, and in its epilogue keeps
 // for each column (p, g) only the rows i whose label is g:
 //     z[item][p][g] = sum_{i in panel, g_p(i) = g} Y[i][(p, g)].
 // Each (panel, K chunk) work item writes its own z; they are summed in FP64 and
@@ -35,7 +36,6 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr int kPanel = 128;      // rows per panel
 constexpr int kKBlock = 64;      // columns per K block
 constexpr int kUnitU4 = 1024;    // uint4 per (panel, K block) unit per component (16 KB)
-constexpr int kCols = 256;       // N columns per work-group (4 waves x 64)
 
 // bits of 1.0 in the MFMA input type
 template <int DT>
@@ -155,13 +155,22 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 }
 
 // DT: 0 bf16, 1 f16, 2 split bf16 (hi and lo MFMAs into one accumulator).
-template <int DT>
+// NF: 32-column fragments per wave; a work-group of 4 waves covers 128 rows x
+// (4 * NF * 32) columns.  The K blocks of A (the pre-squared tiles) are staged
+// once per work-group in double-buffered LDS and read by all four waves; each
+// wave builds its own one-hot B fragments from u16 labels, one K step ahead.
+template <int DT, int NF>
 __global__ __launch_bounds__(256) void k_mfma(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
     const uint16_t *__restrict__ lab, int64_t n_pad, int32_t k, int64_t P,
     float *__restrict__ z) {
-    constexpr int BT = DT == 1 ? 1 : 0;  // operand type of B
+    constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
+    constexpr int NC = DT == 2 ? 2 : 1;     // A components (hi, lo)
+    constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
+    constexpr int COLS = 4 * NF * 32;       // columns per work-group
+    __shared__ uint4 sA[2][UNIT];
+
     const int64_t gpad = gridDim.x;
     const int64_t bid = blockIdx.x;
     const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
@@ -169,67 +178,104 @@ __global__ __launch_bounds__(256) void k_mfma(
     const int64_t item = logical / nblocks;
     const int64_t nb = logical % nblocks;
     const int64_t I = tab[3 * item], kb0 = tab[3 * item + 1], kb1 = tab[3 * item + 2];
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
     const int half = lane / 32, col = lane % 32;
     const int64_t NK = (int64_t)k * P;
 
-    int64_t cidx[2], pcol[2];
-    int32_t gcol[2];
-    uint32_t gg[2];
-    const uint16_t *labrow[2];
+    int64_t cidx[NF], pcol[NF];
+    int32_t gcol[NF];
+    uint32_t gg[NF];
+    const uint16_t *labrow[NF];
 #pragma unroll
-    for (int nf = 0; nf < 2; nf++) {
-        cidx[nf] = nb * kCols + wave * 64 + nf * 32 + col;
+    for (int nf = 0; nf < NF; nf++) {
+        cidx[nf] = nb * COLS + wave * (NF * 32) + nf * 32 + col;
         pcol[nf] = cidx[nf] / k;
         gcol[nf] = (int32_t)(cidx[nf] % k);
         gg[nf] = (uint32_t)gcol[nf] | ((uint32_t)gcol[nf] << 16);
-        labrow[nf] = lab + pcol[nf] * n_pad;
+        labrow[nf] = lab + pcol[nf] * n_pad + 32 * half;
     }
 
-    f32x16 acc[4][2];
+    f32x16 acc[4][NF];
 #pragma unroll
     for (int rb = 0; rb < 4; rb++)
 #pragma unroll
-        for (int nf = 0; nf < 2; nf++)
+        for (int nf = 0; nf < NF; nf++)
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[rb][nf][v] = 0.0f;
 
     const int64_t panel_off = I * kb_total - I * (I - 1);
+    // Direct global -> LDS copy of one staged K block: lane l of wave w moves
+    // uint4 number q*256 + 64w + l of the block (both sides in fragment order).
+    auto stage = [&](int64_t kb, int buf) {
+#pragma unroll
+        for (int q = 0; q < UNIT / 256; q++) {
+            const uint4 *src = tiles + ((int64_t)(q / 4) * comp_units + panel_off + (kb - 2 * I)) *
+                                           kUnitU4 + (q % 4) * 256 + tid;
+            __builtin_amdgcn_global_load_lds(
+                (__attribute__((address_space(1))) void *)src,
+                (__attribute__((address_space(3))) void *)&sA[buf][q * 256 + wave * 64], 16, 0, 0);
+        }
+    };
+    stage(kb0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    uint4 L[NF];
+#pragma unroll
+    for (int nf = 0; nf < NF; nf++) L[nf] = *(const uint4 *)(labrow[nf] + kb0 * kKBlock);
+
     for (int64_t kb = kb0; kb < kb1; kb++) {
-        const uint4 *U = tiles + (panel_off + (kb - 2 * I)) * kUnitU4;
-        const int64_t jb = kb * kKBlock + 32 * half;
+        const int buf = (int)((kb - kb0) & 1);
+        const bool more = kb + 1 < kb1;
+        // The other buffer was last read before the previous barrier.
+        if (more) stage(kb + 1, buf ^ 1);
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            uint4 B[2];
+            uint4 B[NF];
 #pragma unroll
-            for (int nf = 0; nf < 2; nf++)
-                B[nf] = onehot8<BT>(*(const uint4 *)(labrow[nf] + jb + 8 * s), gg[nf]);
+            for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(L[nf], gg[nf]);
+            // labels of the next K step (or the next K block's first step)
+            if (s < 3) {
+#pragma unroll
+                for (int nf = 0; nf < NF; nf++)
+                    L[nf] = *(const uint4 *)(labrow[nf] + kb * kKBlock + 8 * (s + 1));
+            } else if (more) {
+#pragma unroll
+                for (int nf = 0; nf < NF; nf++)
+                    L[nf] = *(const uint4 *)(labrow[nf] + (kb + 1) * kKBlock);
+            }
 #pragma unroll
             for (int rb = 0; rb < 4; rb++) {
-                const uint4 A = U[(rb * 4 + s) * 64 + lane];
 #pragma unroll
-                for (int nf = 0; nf < 2; nf++) acc[rb][nf] = mma<BT>(A, B[nf], acc[rb][nf]);
-                if (DT == 2) {
-                    const uint4 Al = U[comp_units * kUnitU4 + (rb * 4 + s) * 64 + lane];
+                for (int c = 0; c < NC; c++) {
+                    const uint4 A = sA[buf][c * kUnitU4 + (rb * 4 + s) * 64 + lane];
 #pragma unroll
-                    for (int nf = 0; nf < 2; nf++) acc[rb][nf] = mma<BT>(Al, B[nf], acc[rb][nf]);
+                    for (int nf = 0; nf < NF; nf++) acc[rb][nf] = mma<BT>(A, B[nf], acc[rb][nf]);
                 }
             }
         }
+        // the next block's copy has landed in LDS for every wave
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
 
     // Epilogue: keep the rows whose label equals the column's group.
     const int64_t i0 = I * kPanel;
 #pragma unroll
-    for (int nf = 0; nf < 2; nf++) {
+    for (int nf = 0; nf < NF; nf++) {
+        const uint16_t *lr = lab + pcol[nf] * n_pad + i0;
         float zs = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int r = rb * 32 + 8 * (v / 4) + 4 * half + (v % 4);
-                const uint32_t li = labrow[nf][i0 + r];
-                zs += (li == (uint32_t)gcol[nf]) ? acc[rb][nf][v] : 0.0f;
+            for (int a = 0; a < 4; a++) {
+                // rows rb*32 + 8a + 4*half + 0..3 of the panel
+                const uint2 l4 = *(const uint2 *)(lr + rb * 32 + 8 * a + 4 * half);
+                const uint32_t lab4[4] = {l4.x & 0xFFFFu, l4.x >> 16, l4.y & 0xFFFFu, l4.y >> 16};
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    zs += (lab4[b] == (uint32_t)gcol[nf]) ? acc[rb][nf][4 * a + b] : 0.0f;
             }
         }
         zs += __shfl_xor(zs, 32);
@@ -253,17 +299,16 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     pl.n_pad = round_up(n, kPanel);
     pl.panels = pl.n_pad / kPanel;
     pl.kb_total = pl.n_pad / kKBlock;
-    int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock : 32;
+    int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock : 16;
     if (kc < 1) kc = 1;
     pl.kchunk = kc;
     int64_t items = 0;
     for (int64_t I = 0; I < pl.panels; I++) items += ceil_div(pl.kb_total - 2 * I, kc);
     pl.items = items;
-    pl.ncols = kCols;
-    (void)ncols;
+    pl.ncols = (ncols == 256) ? 256 : 512;
     pl.N = (int64_t)k * P;
-    pl.nblocks = ceil_div(pl.N > 0 ? pl.N : 1, kCols);
-    pl.P_pad = ceil_div(pl.nblocks * kCols, k);
+    pl.nblocks = ceil_div(pl.N > 0 ? pl.N : 1, pl.ncols);
+    pl.P_pad = ceil_div(pl.nblocks * pl.ncols, k);
     if (pl.P_pad < P) pl.P_pad = P;
     pl.tile_bytes = mfma_tile_bytes(n, dtype);
     return pl;
@@ -282,25 +327,36 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     else hipLaunchKernelGGL(k_prepass<2>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, t);
 }
 
+template <int DT, int NF>
+void launch_mfma_t(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
+                   int64_t grid_real, int64_t gpad, const uint16_t *lab, int32_t k, int64_t P,
+                   float *z, hipStream_t s) {
+    hipLaunchKernelGGL((k_mfma<DT, NF>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
+                       pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad, k, P, z);
+}
+
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
                 int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s) {
     (void)n;
-    if (pl.ncols != kCols) return -1;
+    if (pl.ncols != 256 && pl.ncols != 512) return -1;
     hipLaunchKernelGGL(k_item_table, dim3(1), dim3(64), 0, s, pl.panels, pl.kb_total, pl.kchunk, tab);
     const int64_t grid_real = pl.items * pl.nblocks;
     const int64_t gpad = round_up(grid_real, 8);
     const int64_t comp_units = pl.panels * (pl.panels + 1);
     const uint4 *t = (const uint4 *)tiles;
-    if (pl.dtype == 0)
-        hipLaunchKernelGGL(k_mfma<0>, dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
-                           pl.kb_total, tab, grid_real, pl.nblocks, lab_pm, pl.n_pad, k, P, z);
-    else if (pl.dtype == 1)
-        hipLaunchKernelGGL(k_mfma<1>, dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
-                           pl.kb_total, tab, grid_real, pl.nblocks, lab_pm, pl.n_pad, k, P, z);
-    else
-        hipLaunchKernelGGL(k_mfma<2>, dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
-                           pl.kb_total, tab, grid_real, pl.nblocks, lab_pm, pl.n_pad, k, P, z);
-    return 0;
+#define PSTAT_MFMA_CASE(DT_)                                                                   \
+    if (pl.dtype == DT_) {                                                                     \
+        if (pl.ncols == 512)                                                                   \
+            launch_mfma_t<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
+        else                                                                                   \
+            launch_mfma_t<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
+        return 0;                                                                              \
+    }
+    PSTAT_MFMA_CASE(0)
+    PSTAT_MFMA_CASE(1)
+    PSTAT_MFMA_CASE(2)
+#undef PSTAT_MFMA_CASE
+    return -1;
 }
 
 } // namespace pstat

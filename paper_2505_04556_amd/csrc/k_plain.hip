@@ -21,6 +21,7 @@ namespace pstat {
 namespace {
 
 constexpr int kWeightCache = 1024;  // weights held in LDS (k up to this many)
+constexpr int64_t kMaxChunks = 2048;  // partial rows per permutation (bounds the reduction)
 
 // Upper-triangle tile t (row-major over tile rows I, J = I .. nt-1) -> (I, J).
 __device__ inline void tri_decode(int64_t t, int64_t nt, int64_t &I, int64_t &J) {
@@ -134,7 +135,7 @@ void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t
 
 } // namespace
 
-PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu, int64_t plan_P) {
+PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu) {
     PlainPlan pl{};
     pl.tile = tile;
     pl.lanes = lanes;
@@ -145,8 +146,8 @@ PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu, int64_
     pl.pgroups = pl.P_pad / lanes;
     // Enough work-groups to fill every CU several times over.
     const int64_t target = (int64_t)(n_cu > 0 ? n_cu : 256) * 32;
-    const int64_t plan_groups = plan_P > P ? ceil_div(plan_P, lanes) : pl.pgroups;
-    int64_t chunks = ceil_div(target, plan_groups);
+    int64_t chunks = ceil_div(target, pl.pgroups);
+    if (chunks > kMaxChunks) chunks = kMaxChunks;
     if (chunks > pl.n_tiles) chunks = pl.n_tiles;
     if (chunks < 1) chunks = 1;
     pl.tiles_per_chunk = ceil_div(pl.n_tiles, chunks);

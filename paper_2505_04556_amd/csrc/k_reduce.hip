@@ -22,6 +22,7 @@ __global__ void k_reduce_plain(const double *__restrict__ partial, int64_t chunk
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
          p += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
+#pragma unroll 8
         for (int64_t c = 0; c < chunks; c++) s += partial[c * P_pad + p];
         out[p] = (bad_perm && bad_perm[p]) ? NAN : s;
     }
@@ -81,18 +82,40 @@ __global__ __launch_bounds__(1024) void k_pvalue(const double *__restrict__ obs,
     if (threadIdx.x == 0) *p = P > 0 ? (double)(1 + red[0]) / (double)(1 + P) : NAN;
 }
 
-__global__ void k_flag_ties(const double *__restrict__ sW_all, int64_t P, double band,
-                            int32_t *__restrict__ list, int32_t *__restrict__ count) {
+// rows q in [q0, R) of sW_all with |sW_all[q] - sW_all[0]| <= *band * |sW_all[0]|
+// are appended to list.
+__global__ void k_flag_ties(const double *__restrict__ sW_all, int64_t q0, int64_t R,
+                            const double *__restrict__ band, int32_t *__restrict__ list,
+                            int32_t *__restrict__ count) {
     const double o = sW_all[0];
-    const double tol = band * fabs(o);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
+    const double tol = *band * fabs(o);
+    for (int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < R;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const double v = sW_all[1 + q];
-        if (fabs(v - o) <= tol) {
+        if (fabs(sW_all[q] - o) <= tol) {
             const int32_t at = atomicAdd(count, 1);
-            list[at] = (int32_t)(1 + q);
+            list[at] = (int32_t)q;
         }
     }
+}
+
+// *band = margin * max_j |fast[j] - exact[j]| / |exact[0]| over the S samples
+// (exact = FP64 recomputation), at least 1e-13.
+__global__ void k_tie_band(const double *__restrict__ fast, const double *__restrict__ exact,
+                           int64_t S, double margin, double *__restrict__ band) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double e = 0.0;
+    for (int64_t j = 0; j < S; j++) {
+        const double d = fabs(fast[j] - exact[j]);
+        e = (d > e || d != d) ? d : e;  // NaN propagates
+    }
+    const double b = margin * e / fabs(exact[0]);
+    *band = (b > 1e-13 || b != b) ? b : 1e-13;
+}
+
+__global__ void k_iota(int32_t *__restrict__ list, int64_t m) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        list[i] = (int32_t)i;
 }
 
 __global__ void k_scatter(const double *__restrict__ vals, const int32_t *__restrict__ list,
@@ -142,11 +165,21 @@ void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, doubl
     hipLaunchKernelGGL(k_pvalue, dim3(1), dim3(1024), 0, s, sW_obs, sW_perm, P, p);
 }
 
-void launch_flag_ties(const double *sW_all, int64_t P, double band, int32_t *list,
-                      int32_t *count, hipStream_t s) {
-    if (P <= 0) return;
-    hipLaunchKernelGGL(k_flag_ties, dim3(blocks_for(P, 256)), dim3(256), 0, s, sW_all, P, band,
-                       list, count);
+void launch_flag_ties(const double *sW_all, int64_t q0, int64_t R, const double *band,
+                      int32_t *list, int32_t *count, hipStream_t s) {
+    if (R <= q0) return;
+    hipLaunchKernelGGL(k_flag_ties, dim3(blocks_for(R - q0, 256)), dim3(256), 0, s, sW_all, q0, R,
+                       band, list, count);
+}
+
+void launch_tie_band(const double *fast, const double *exact, int64_t S, double margin,
+                     double *band, hipStream_t s) {
+    hipLaunchKernelGGL(k_tie_band, dim3(1), dim3(64), 0, s, fast, exact, S, margin, band);
+}
+
+void launch_iota(int32_t *list, int64_t m, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, list, m);
 }
 
 void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *sW_all,

@@ -11,15 +11,14 @@ __device__ inline int32_t wave_max(int32_t v) {
     return v;
 }
 
-// Checks one label; returns the u16 to store.
+// Checks one label; returns the u16 to store (the pad value for a bad one).
 __device__ inline uint16_t check_label(int32_t v, int32_t limit, int64_t p, uint8_t *bad_perm,
-                                       int32_t *err_flag, int32_t &local_max) {
+                                       int32_t *err_flag) {
     if (v < 0 || v >= limit) {
         bad_perm[p] = 1;
         atomicOr(err_flag, 1);
         return kPadLabel;
     }
-    local_max = max(local_max, v);
     return (uint16_t)v;
 }
 
@@ -28,19 +27,17 @@ __device__ inline uint16_t check_label(int32_t v, int32_t limit, int64_t p, uint
 __global__ __launch_bounds__(256) void k_stage_labels_om(
     const int32_t *__restrict__ g, const int32_t *__restrict__ rows, int64_t n, int64_t P,
     int64_t n_pad, int64_t P_pad, int32_t limit, uint16_t *__restrict__ out,
-    uint8_t *__restrict__ bad_perm, int32_t *__restrict__ err_flag,
-    int32_t *__restrict__ max_label) {
+    uint8_t *__restrict__ bad_perm, int32_t *__restrict__ err_flag) {
     __shared__ uint16_t tile[64][65];
     const int64_t i0 = (int64_t)blockIdx.x * 64;  // objects
     const int64_t p0 = (int64_t)blockIdx.y * 64;  // permutations
     const int tx = threadIdx.x, ty = threadIdx.y;
-    int32_t local_max = -1;
     for (int r = ty; r < 64; r += 4) {
         const int64_t p = p0 + r, i = i0 + tx;
         uint16_t v = kPadLabel;
         if (p < P && i < n) {
             const int64_t src = rows ? (int64_t)rows[p] : p;
-            v = check_label(g[src * n + i], limit, p, bad_perm, err_flag, local_max);
+            v = check_label(g[src * n + i], limit, p, bad_perm, err_flag);
         }
         tile[r][tx] = v;
     }
@@ -49,26 +46,20 @@ __global__ __launch_bounds__(256) void k_stage_labels_om(
         const int64_t i = i0 + r, p = p0 + tx;
         if (i < n_pad && p < P_pad) out[i * P_pad + p] = tile[tx][r];
     }
-    local_max = wave_max(local_max);
-    if ((threadIdx.x & 63) == 0 && local_max >= 0) atomicMax(max_label, local_max);
 }
 
 __global__ __launch_bounds__(256) void k_stage_labels_pm(
     const int32_t *__restrict__ g, int64_t n, int64_t P, int64_t n_pad, int64_t P_pad,
     int32_t limit, uint16_t *__restrict__ out, uint8_t *__restrict__ bad_perm,
-    int32_t *__restrict__ err_flag, int32_t *__restrict__ max_label) {
-    int32_t local_max = -1;
+    int32_t *__restrict__ err_flag) {
     for (int64_t p = blockIdx.y; p < P_pad; p += gridDim.y) {
         for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_pad;
              i += (int64_t)gridDim.x * 256) {
             uint16_t v = kPadLabel;
-            if (p < P && i < n)
-                v = check_label(g[p * n + i], limit, p, bad_perm, err_flag, local_max);
+            if (p < P && i < n) v = check_label(g[p * n + i], limit, p, bad_perm, err_flag);
             out[p * n_pad + i] = v;
         }
     }
-    local_max = wave_max(local_max);
-    if ((threadIdx.x & 63) == 0 && local_max >= 0) atomicMax(max_label, local_max);
 }
 
 // Flat range check and maximum of int32 labels.
@@ -85,7 +76,13 @@ __global__ __launch_bounds__(256) void k_scan_labels(const int32_t *__restrict__
     }
     if (bad) atomicOr(err_flag, 1);
     local_max = wave_max(local_max);
-    if ((threadIdx.x & 63) == 0 && local_max >= 0) atomicMax(max_label, local_max);
+    __shared__ int32_t wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = local_max;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        if (m >= 0) atomicMax(max_label, m);
+    }
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t count, uint8_t v) {
@@ -165,11 +162,10 @@ inline unsigned grid_for(int64_t count, int block, int64_t cap = 65535) {
 
 void launch_stage_labels_om(const int32_t *g, const int32_t *rows, int64_t n, int64_t P,
                             int64_t n_pad, int64_t P_pad, int32_t limit, uint16_t *out,
-                            uint8_t *bad_perm, int32_t *err_flag, int32_t *max_label,
-                            hipStream_t s) {
+                            uint8_t *bad_perm, int32_t *err_flag, hipStream_t s) {
     dim3 grid((unsigned)ceil_div(n_pad, 64), (unsigned)ceil_div(P_pad, 64));
     hipLaunchKernelGGL(k_stage_labels_om, grid, dim3(64, 4), 0, s, g, rows, n, P, n_pad, P_pad,
-                       limit, out, bad_perm, err_flag, max_label);
+                       limit, out, bad_perm, err_flag);
 }
 
 void launch_scan_labels(const int32_t *g, int64_t count, int32_t limit, int32_t *err_flag,
@@ -181,10 +177,10 @@ void launch_scan_labels(const int32_t *g, int64_t count, int32_t limit, int32_t 
 
 void launch_stage_labels_pm(const int32_t *g, int64_t n, int64_t P, int64_t n_pad,
                             int64_t P_pad, int32_t limit, uint16_t *out, uint8_t *bad_perm,
-                            int32_t *err_flag, int32_t *max_label, hipStream_t s) {
+                            int32_t *err_flag, hipStream_t s) {
     dim3 grid(grid_for(n_pad, 256, 64), (unsigned)(P_pad < 65535 ? P_pad : 65535));
     hipLaunchKernelGGL(k_stage_labels_pm, grid, dim3(256), 0, s, g, n, P, n_pad, P_pad, limit,
-                       out, bad_perm, err_flag, max_label);
+                       out, bad_perm, err_flag);
 }
 
 void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s) {

@@ -45,6 +45,9 @@ struct Thread {
     int32_t *flags = nullptr;
     int flags_device = -1;
     int32_t *host_flags = nullptr;  // pinned
+    // main-kernel timing (pstat_profile)
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     char err[512] = {0};
 };
 
@@ -179,17 +182,19 @@ int resolve_path(int path) {
     return PSTAT_PATH_PLAIN_F32;
 }
 
-void plain_params(int path, int *tile, int *lanes) {
+void plain_params(int path, int64_t P, int *tile, int *lanes) {
     const Tuning &t = tls.tuning[path];
     *tile = t.tile ? t.tile : 32;
-    *lanes = t.batch ? t.batch : 256;
+    // Few permutations (the FP64 recheck): narrower work-groups keep more of
+    // the lanes busy.
+    *lanes = t.batch ? t.batch : (P <= 64 ? 64 : P <= 128 ? 128 : 256);
     if (path == PSTAT_PATH_PLAIN_F64 && *tile > 32) *tile = 32;
 }
 
 void mfma_params(int path, int *kchunk_cols, int *ncols) {
     const Tuning &t = tls.tuning[path];
     *kchunk_cols = t.tile;   // 0 = planner's choice
-    *ncols = t.batch ? t.batch : 256;
+    *ncols = t.batch ? t.batch : 512;
 }
 
 // ---- s_W on a staged problem ------------------------------------------------
@@ -208,13 +213,13 @@ struct SwLayout {
 };
 
 void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
-               SwLayout &L, int64_t plan_P = 0) {
+               SwLayout &L) {
     L.path = path;
     L.bad = (uint8_t *)c.take((size_t)(P > 0 ? P : 1));
     if (!is_mfma(path)) {
         int tile, lanes;
-        plain_params(path, &tile, &lanes);
-        L.pp = plain_plan(n, P, tile, lanes, dev_info().n_cu, plan_P);
+        plain_params(path, P, &tile, &lanes);
+        L.pp = plain_plan(n, P, tile, lanes, dev_info().n_cu);
         L.lab = (uint16_t *)c.take((size_t)L.pp.n_pad * L.pp.P_pad * sizeof(uint16_t));
         L.partial = (double *)c.take((size_t)L.pp.chunks * L.pp.P_pad * sizeof(double));
         return;
@@ -236,39 +241,75 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
     return c.used + 256;
 }
 
+// Upper bound of sW_bytes over every P' <= P on a plain path (the plan's
+// chunk count depends on P', but chunks * P_pad stays below
+// (target + P/64 + 1) * 256).
+size_t plain_bytes_bound(int64_t n, int64_t P, int path) {
+    size_t b = 0;
+    for (int64_t q : {P, (int64_t)1, (int64_t)64, (int64_t)128, (int64_t)256})
+        if (q <= P) b = b > sW_bytes(n, q, 1, path, false) ? b : sW_bytes(n, q, 1, path, false);
+    const int64_t target = (int64_t)dev_info().n_cu * 32;
+    const size_t partial = (size_t)(target + P / 64 + 2) * 256 * sizeof(double);
+    const size_t labels = (size_t)round_up(n, 64) * round_up(P, 256) * sizeof(uint16_t);
+    const size_t bound = (size_t)P + partial + labels + 4 * 256;
+    return b > bound ? b : bound;
+}
+
 // Runs one evaluation: stage labels (row q of the staged problem is row
 // rows[q] of g, or row q when rows is NULL; rows is only used by plain paths),
 // run the kernel, reduce into out[0..P).  tiles: pre-squared tiles of a
 // registered matrix, or NULL to run the pre-pass into L.tiles.
+// Event pair around the main kernel when this thread is profiling.
+struct KernelTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(hipStream_t s, bool timed) {
+        if (!tls.profiling || !timed) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            (void)hipGetLastError();
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    void stop(hipStream_t s) {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        tls.events.emplace_back(a, b);
+        a = b = nullptr;
+    }
+};
+
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
-            double *out, const void *tiles, int32_t *err_flag) {
+            double *out, const void *tiles, int32_t *err_flag, bool timed = true) {
     hipStream_t s = tls.stream;
-    int32_t *maxl = tls.flags + 1;
     int rc;
     launch_fill_u8(L.bad, P, 0, s);
-    launch_fill_i32(maxl, 1, -1, s);
     if (!is_mfma(L.path)) {
         launch_stage_labels_om(g, rows, n, P, L.pp.n_pad, L.pp.P_pad, limit, L.lab, L.bad,
-                               err_flag, maxl, s);
+                               err_flag, s);
         if ((rc = check_launch("label staging"))) return rc;
+        KernelTimer timer(s, timed);
         if (launch_plain(L.pp, L.path == PSTAT_PATH_PLAIN_F64, mat, n, L.lab, w, k, L.partial, s))
             return fail(PSTAT_EINVAL, "no plain kernel for tile %d, lanes %d", L.pp.tile,
                         L.pp.lanes);
+        timer.stop(s);
         if ((rc = check_launch("plain s_W"))) return rc;
         launch_reduce_plain(L.partial, L.pp.chunks, L.pp.P_pad, P, L.bad, out, s);
         return check_launch("plain reduce");
     }
     if (rows) return fail(PSTAT_EINVAL, "row lists are only supported on the plain paths");
-    launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, maxl, s);
+    launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, s);
     if ((rc = check_launch("label staging"))) return rc;
     if (!tiles) {
         launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s);
         if ((rc = check_launch("mfma prepass"))) return rc;
         tiles = L.tiles;
     }
+    KernelTimer timer(s, timed);
     if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s))
         return fail(PSTAT_EINVAL, "no MFMA kernel for %d columns", L.mp.ncols);
+    timer.stop(s);
     if ((rc = check_launch("mfma s_W"))) return rc;
     launch_reduce_mfma(L.z, L.mp.items, P, k, w, L.bad, L.tmp, out, s);
     return check_launch("mfma reduce");
@@ -328,15 +369,11 @@ int init_flags() {
     return PSTAT_OK;
 }
 
-double tie_band(int path) {
-    switch (path) {
-        case PSTAT_PATH_PLAIN_F32: return 1e-6;
-        case PSTAT_PATH_MFMA_SPLIT_BF16: return 2e-5;
-        case PSTAT_PATH_MFMA_F16: return 2e-3;
-        case PSTAT_PATH_MFMA_BF16: return 1e-2;
-        default: return 0.0;
-    }
-}
+// Tie band of the p-value recheck: kBandMargin times the largest relative
+// error of the fast path over the observed grouping and the first
+// kBandSamples permutations (all recomputed in FP64).
+constexpr int64_t kBandSamples = 15;
+constexpr double kBandMargin = 16.0;
 
 } // namespace
 
@@ -391,8 +428,8 @@ int pstat_set_tuning(int path, int tile, int batch) {
     if (path < 0 || path >= PSTAT_N_PATHS) return fail(PSTAT_EINVAL, "unknown path %d", path);
     if (is_mfma(path)) {
         if (tile < 0 || tile % 64) return fail(PSTAT_EINVAL, "K chunk must be a multiple of 64");
-        if (batch != 0 && batch != 128 && batch != 256)
-            return fail(PSTAT_EINVAL, "MFMA N columns must be 128 or 256");
+        if (batch != 0 && batch != 256 && batch != 512)
+            return fail(PSTAT_EINVAL, "MFMA N columns must be 256 or 512");
     } else {
         if (tile != 0 && tile != 32 && tile != 64) return fail(PSTAT_EINVAL, "tile must be 32 or 64");
         if (path == PSTAT_PATH_PLAIN_F64 && tile == 64)
@@ -539,7 +576,7 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     // evaluation and by the FP64 recheck.
     auto carve_head = [&](Carver &c, int32_t *&allg, double *&w, uint32_t *&counts,
                           double *&sw, double *&sTp, double *&pv, int32_t *&list,
-                          double *&vals) {
+                          double *&vals, double *&band) {
         allg = (int32_t *)c.take((size_t)R * n * sizeof(int32_t));
         w = (double *)c.take((size_t)k * sizeof(double));
         counts = (uint32_t *)c.take((size_t)k * sizeof(uint32_t));
@@ -548,20 +585,21 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         pv = (double *)c.take(sizeof(double));
         list = (int32_t *)c.take((size_t)R * sizeof(int32_t));
         vals = (double *)c.take((size_t)R * sizeof(double));
+        band = (double *)c.take(sizeof(double));
     };
     int32_t *allg, *list;
-    double *w, *sw, *sTp, *pv, *vals;
+    double *w, *sw, *sTp, *pv, *vals, *band;
     uint32_t *counts;
     Carver dry{nullptr, 0, 0, true};
-    carve_head(dry, allg, w, counts, sw, sTp, pv, list, vals);
+    carve_head(dry, allg, w, counts, sw, sTp, pv, list, vals, band);
     const size_t head = dry.used + 256;
     size_t region = sW_bytes(n, R, k, path, true);
-    const size_t region64 = sW_bytes(n, R, k, PSTAT_PATH_PLAIN_F64, true);
+    const size_t region64 = plain_bytes_bound(n, R, PSTAT_PATH_PLAIN_F64);
     if (region64 > region) region = region64;
     char *ws;
     if ((rc = acquire_workspace(head + region, &ws))) return rc;
     Carver hc{ws, head, 0, false};
-    carve_head(hc, allg, w, counts, sw, sTp, pv, list, vals);
+    carve_head(hc, allg, w, counts, sw, sTp, pv, list, vals, band);
     double *sT = sTp + nsT;
     if (sW_all) sw = sW_all;
 
@@ -579,31 +617,45 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     launch_sT(mat, n, sTp, sT, s);
     if ((rc = check_launch("s_T"))) return rc;
 
-    // Recheck in FP64: the observed grouping always (it gives F_obs), and every
-    // permutation whose s_W lies within the path's error band of the observed
-    // value, so that the p-value count is decided at FP64 accuracy.
+    // FP64 recheck.  First the observed grouping and the first few
+    // permutations: the observed value gives F_obs, and the largest relative
+    // error of the fast path over these samples sets the tie band.  Then every
+    // permutation whose fast s_W lies within the band of the observed value is
+    // recomputed, so that the p-value count is decided at FP64 accuracy.
     int64_t rechecked = 0;
-    const double band = tie_band(path);
-    if (band > 0.0) {
+    if (path != PSTAT_PATH_PLAIN_F64) {
+        const int64_t S = (n_perms < kBandSamples ? n_perms : kBandSamples) + 1;
+        launch_iota(list, S, s);
+        {
+            Carver c{ws + head, region, 0, false};
+            SwLayout L;
+            layout_sW(c, n, S, k, PSTAT_PATH_PLAIN_F64, true, L);
+            if ((rc = exec_sW(L, mat, n, allg, list, S, k, k, w, vals, nullptr, tls.flags, false)))
+                return rc;
+        }
+        launch_tie_band(sw, vals, S, kBandMargin, band, s);
+        launch_scatter(vals, list, S, sw, s);
+        if ((rc = check_launch("tie band"))) return rc;
         int64_t m = 0;
-        if (n_perms > 0) {
+        if (n_perms >= S) {
             launch_fill_i32(tls.flags + 2, 1, 0, s);
-            launch_flag_ties(sw, n_perms, band, list + 1, tls.flags + 2, s);
+            launch_flag_ties(sw, S, R, band, list, tls.flags + 2, s);
             if ((rc = check_launch("tie flags"))) return rc;
             HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, 3 * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             m = tls.host_flags[2];
         }
-        const int64_t M = m + 1;
-        launch_fill_i32(list, 1, 0, s);
-        Carver c{ws + head, region, 0, false};
-        SwLayout L;
-        layout_sW(c, n, M, k, PSTAT_PATH_PLAIN_F64, true, L, R);
-        if ((rc = exec_sW(L, mat, n, allg, list, M, k, k, w, vals, nullptr, tls.flags))) return rc;
-        launch_scatter(vals, list, M, sw, s);
-        if ((rc = check_launch("recheck scatter"))) return rc;
-        rechecked = m;
+        if (m > 0) {
+            Carver c{ws + head, region, 0, false};
+            SwLayout L;
+            layout_sW(c, n, m, k, PSTAT_PATH_PLAIN_F64, true, L);
+            if ((rc = exec_sW(L, mat, n, allg, list, m, k, k, w, vals, nullptr, tls.flags, false)))
+                return rc;
+            launch_scatter(vals, list, m, sw, s);
+            if ((rc = check_launch("recheck scatter"))) return rc;
+        }
+        rechecked = S - 1 + m;
     }
     launch_pvalue(sw, sw + 1, n_perms, pv, s);
     launch_pack_result(sw, sT, n, k, pv, result, s);
@@ -665,6 +717,29 @@ int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perm
     if (r.device != tls.device) return fail(PSTAT_EINVAL, "handle belongs to device %d", r.device);
     return sW_common(r.mat, r.n, groupings, n_perms, n_groups, inv_group_sizes, out, false,
                      r.tiles, r.path);
+}
+
+int pstat_profile(int on) {
+    for (auto &e : tls.events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    tls.events.clear();
+    tls.profiling = on != 0;
+    return PSTAT_OK;
+}
+
+int pstat_profile_read(double *ms, int64_t *launches) {
+    double total = 0.0;
+    for (auto &e : tls.events) {
+        HIP_TRY(hipEventSynchronize(e.second));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+        total += t;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = (int64_t)tls.events.size();
+    return PSTAT_OK;
 }
 
 }  // extern "C"

@@ -19,7 +19,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            raise ImportError(f"{_LIB_PATH} missing: run `python -m paper_2505_04556_amd.build`")
+            raise ImportError(f"{_LIB_PATH} missing: run `python paper_2505_04556_amd/build.py`")
         L = ctypes.CDLL(_LIB_PATH)
         L.synth_uniform.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p]

@@ -13,12 +13,22 @@ import synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def load_build_module():
+    """The build script, loaded by path (importing the package needs the
+    library it builds)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "pstat_build", os.path.join(ROOT, "paper_2505_04556_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
 def load_pstat():
     lib = os.path.join(ROOT, "paper_2505_04556_amd", "libpstat.so")
     slib = os.path.join(ROOT, "synth", "libsynth.so")
     if not (os.path.exists(lib) and os.path.exists(slib)):
-        from paper_2505_04556_amd import build
-        build.build_all()
+        load_build_module().build_all()
     import paper_2505_04556_amd as pstat
     return pstat
 

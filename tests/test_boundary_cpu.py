@@ -21,8 +21,8 @@ def declared_symbols():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_2505_04556_amd import build
-        build.build_pstat()
+        from gpu_util import load_build_module
+        load_build_module().build_pstat()
     return ctypes.CDLL(LIB)
 
 

@@ -92,12 +92,13 @@ def test_plain_tunings(ps, tile, lanes):
     assert max_rel(got, ref) <= TOL["plain_f32"]
 
 
-@pytest.mark.parametrize("kcols", [64, 128, 512])
-def test_mfma_k_chunks(ps, kcols):
+@pytest.mark.parametrize("path", ["mfma_split_bf16", "mfma_f16", "mfma_bf16"])
+@pytest.mark.parametrize("kcols,ncols", [(64, 256), (128, 512), (512, 256), (0, 512)])
+def test_mfma_tunings(ps, path, kcols, ncols):
     D, base, perms, w = problem(700, [100, 250, 350], 50, mseed=6, pseed=7)
     ref = oracle.sW(D, perms, w)
-    got = run_sW(ps, "mfma_split_bf16", D, perms, w, tuning=(kcols, 256))
-    assert max_rel(got, ref) <= TOL["mfma_split_bf16"]
+    got = run_sW(ps, path, D, perms, w, tuning=(kcols, ncols))
+    assert max_rel(got, ref) <= TOL[path]
 
 
 def test_many_groups(ps):
