@@ -105,6 +105,34 @@ def cpu_baseline(D_host, cfg, target_s=12.0):
                 perms_array=perms)
 
 
+def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
+    """The serving trace: Poisson arrivals (4 requests/s), n in {1k..20k}, k in
+    2..12 with Dirichlet sizes, 999 or 9,999 permutations; continuous batching
+    under an HBM budget.  Latency = result time - arrival time."""
+    import synth
+    import synth.device as sd
+    from paper_2505_04556_amd.serve import GpuExecutor, Request, Server
+    reqs = []
+    for t in synth.serving_requests(count, rate, 4000):
+        reqs.append(Request(id=t["id"], n=t["n"], k=t["k"], grouping=synth.base_labels(t["sizes"]),
+                            n_perms=t["n_perms"], seed=t["perm_seed"], arrival=t["arrival"],
+                            make_matrix=(lambda dev, n=t["n"], s=t["matrix_seed"]:
+                                         sd.uniform_matrix(n, s, dev))))
+    ex = GpuExecutor(max_jobs=32, max_units=8192)
+    try:
+        srv = Server(ex, hbm_budget=budget_bytes, round_work=1.5e11, max_units=8192)
+        res = srv.run(reqs)
+    finally:
+        ex.close()
+    st = dict(res["stats"])
+    waited = sum(1 for o in res["outcomes"].values()
+                 if o.error is None and o.admitted - o.arrival > 0.05)
+    st.update(rounds=res["rounds"], peak_resident_GB=round(res["peak_bytes"] / 1e9, 3),
+              budget_GB=round(budget_bytes / 1e9, 3), requests=count, arrivals_per_s=rate,
+              admissions_delayed_50ms=waited, quantiles="nearest rank", path="plain_f32 work-list")
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +141,8 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--paths", default="plain_f32,mfma_split_bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the permutation "
@@ -149,6 +179,13 @@ def main() -> int:
         cpu = cpu_baseline(D.cpu().numpy(), cfg)
         log(f"  oracle: {cpu['value']:.3f} G pair-perms/s on {cpu['threads']} threads, "
             f"{cpu['perms']} perms in {cpu['seconds']:.1f} s")
+
+    serve = None
+    if not args.no_serve:
+        log("serving trace: 64 requests, Poisson 4/s")
+        serve = serve_leg(int(args.serve_budget_gb * 1e9))
+        log(f"  serve: p50 {serve.get('p50_s')} s, p99 {serve.get('p99_s')} s, "
+            f"{serve.get('G_pair_perms_per_s')} G pair-perms/s")
 
     # Accuracy of each timed run on the oracle's sample (same generator, same seed).
     acc = {}
@@ -205,6 +242,8 @@ def main() -> int:
                       "max_rel_err_vs_oracle_sample": acc.get(p)}
                   for p, v in runs.items()},
     }
+    if serve is not None:
+        out["serve"] = serve
     if cpu is not None:
         out["cpu_baseline"] = {"value": round(cpu["value"], 4), "unit": "G pair-perms/s",
                                "cores": cpu["threads"], "kind": "oracle",

@@ -164,6 +164,50 @@ int pstat_matrix_release(int64_t handle);
 int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perms,
                         int32_t n_groups, const double *inv_group_sizes, double *out);
 
+/* ---- many tests at once (serving) ----------------------------------------- */
+/* Not part of the paper's statement of the problem: the device side of a
+ * serving loop that keeps several permutation tests resident and runs their
+ * work in shared launches.  A job is one whole test (as pstat_permanova) on
+ * the plain FP32 kernel with tile 32 and 256 permutation lanes; its work is
+ * n_units units (one work-group each).  A round runs any list of units of any
+ * live jobs in one launch of a work-list kernel, replayed from a captured
+ * hipGraph (two graphs alternate, so a round's unit list can be filled while
+ * the previous round runs).  A job's result depends only on its own units and
+ * a fixed reduction order: it is bit-identical alone and in any mix. */
+
+/* Server with room for max_jobs live jobs and max_units units per round. */
+int pstat_serve_create(int64_t max_jobs, int64_t max_units, int64_t *server);
+/* Waits for its rounds, frees the server (job scratch stays the caller's). */
+int pstat_serve_destroy(int64_t server);
+
+/* Device scratch bytes one job needs (caller-owned, kept until release). */
+size_t pstat_job_bytes(int64_t n, int64_t n_perms, int32_t n_groups);
+
+/* Stage a test into `scratch`: validates `grouping` (SYNCHRONISES the stream),
+ * weights, the n_perms shuffles of pstat_permute(seed), staged labels.  mat
+ * must stay valid until release.  *job: the job's id; *n_units: its units,
+ * numbered 0 .. n_units-1. */
+int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t *grouping,
+                     int32_t n_groups, int64_t n_perms, uint64_t seed, void *scratch,
+                     size_t scratch_bytes, int64_t *job, int64_t *n_units);
+
+/* Run `count` units (host array of (job, unit) pairs, 2*count int64) in one
+ * launch on the thread's stream (which must not be the null stream).  Returns
+ * once the launch is queued; waits only for the round that used the same
+ * unit buffer two rounds ago.  Each unit of a job must run exactly once before
+ * pstat_job_finish. */
+int pstat_serve_round(int64_t server, const int64_t *units, int64_t count);
+
+/* After all of a job's units have run: FP64 reduction, s_T, FP64 recheck of
+ * the observed grouping and near ties, F and p.  SYNCHRONISES the stream.
+ * result (HOST, 4 doubles) = {F_obs, p, s_W_obs, s_T}; sW_all (device, may be
+ * NULL) receives s_W of the observed grouping then of each shuffle. */
+int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all,
+                     int64_t *n_rechecked);
+
+/* Free the job's slot (waits for rounds still in flight). */
+int pstat_job_release(int64_t server, int64_t job);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* While enabled (on != 0), every s_W evaluation on this thread records a pair

@@ -84,6 +84,15 @@ _SIGS = {
     "pstat_matrix_register": ([_P, _i64, _int, ctypes.POINTER(_i64)], _int),
     "pstat_matrix_release": ([_i64], _int),
     "pstat_sW_registered": ([_i64, _P, _i64, _i32, _P, _P], _int),
+    "pstat_serve_create": ([_i64, _i64, ctypes.POINTER(_i64)], _int),
+    "pstat_serve_destroy": ([_i64], _int),
+    "pstat_job_bytes": ([_i64, _i64, _i32], _size),
+    "pstat_job_create": ([_i64, _P, _i64, _P, _i32, _i64, _u64, _P, _size, ctypes.POINTER(_i64),
+                          ctypes.POINTER(_i64)], _int),
+    "pstat_serve_round": ([_i64, _P, _i64], _int),
+    "pstat_job_finish": ([_i64, _i64, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(_i64)],
+                         _int),
+    "pstat_job_release": ([_i64, _i64], _int),
     "pstat_profile": ([_int], _int),
     "pstat_profile_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _int),
 }
@@ -276,6 +285,57 @@ def pstat_sW_registered(handle: int, groupings: torch.Tensor, n_groups: int,
                                     _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
                                     _dev(out, torch.float64, "out")))
     return out
+
+
+def pstat_serve_create(max_jobs: int, max_units: int) -> int:
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    h = _i64(0)
+    _check(_lib.pstat_serve_create(int(max_jobs), int(max_units), ctypes.byref(h)))
+    return int(h.value)
+
+
+def pstat_serve_destroy(server: int) -> None:
+    _check(_lib.pstat_serve_destroy(int(server)))
+
+
+def pstat_job_bytes(n: int, n_perms: int, n_groups: int) -> int:
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    return int(_lib.pstat_job_bytes(int(n), int(n_perms), int(n_groups)))
+
+
+def pstat_job_create(server: int, mat: torch.Tensor, grouping: torch.Tensor, n_groups: int,
+                     n_perms: int, seed: int, scratch: torch.Tensor) -> tuple[int, int]:
+    """Returns (job id, number of work units)."""
+    _ready(mat.device)
+    job, units = _i64(0), _i64(0)
+    _check(_lib.pstat_job_create(int(server), _dev(mat, torch.float32, "mat"), mat.shape[0],
+                                 _dev(grouping, torch.int32, "grouping"), int(n_groups),
+                                 int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                 _dev(scratch, torch.uint8, "scratch"), scratch.numel(),
+                                 ctypes.byref(job), ctypes.byref(units)))
+    return int(job.value), int(units.value)
+
+
+def pstat_serve_round(server: int, pairs) -> None:
+    """pairs: int64 numpy array of shape (count, 2) = (job, unit) per row."""
+    import numpy as np
+    arr = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.pstat_serve_round(int(server), arr.ctypes.data if len(arr) else None, len(arr)))
+
+
+def pstat_job_finish(server: int, job: int, sW_all: torch.Tensor | None = None):
+    """Returns ([F_obs, p, s_W_obs, s_T], n_rechecked)."""
+    _ready(torch.device("cuda", torch.cuda.current_device()))
+    res = (ctypes.c_double * 4)()
+    rech = _i64(0)
+    sw = _dev(sW_all, torch.float64, "sW_all") if sW_all is not None else None
+    _check(_lib.pstat_job_finish(int(server), int(job), res, sw, ctypes.byref(rech)))
+    return [float(v) for v in res], int(rech.value)
+
+
+def pstat_job_release(server: int, job: int) -> None:
+    _check(_lib.pstat_job_release(int(server), int(job)))
 
 
 def pstat_profile(on: bool) -> None:

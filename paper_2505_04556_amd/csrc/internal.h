@@ -56,6 +56,23 @@ struct PlainPlan {
     int64_t n_pad;   // n rounded up to T
 };
 PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu);
+
+// Work-list execution (the serving rounds): fixed tile and lanes.
+constexpr int kServeTile = 32;
+constexpr int kServeLanes = 256;
+struct JobDesc {              // one staged problem, device-resident
+    const float *mat;
+    const uint16_t *lab;      // u16 [n_pad][P_pad], object-major
+    const double *w;
+    double *partial;          // [chunks][P_pad]
+    int64_t n, nt, n_tiles, tiles_per_chunk, P_pad;
+    int32_t k, pad;
+};
+struct UnitDesc {             // one work-group's share of one job
+    int32_t job, chunk, pgroup;
+};
+void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
+                           int64_t max_units, hipStream_t s);
 // partial[chunk][P_pad] FP64 from u16 [n_pad][P_pad] labels.  Perm lane q of
 // the label table is permutation q.  f64 selects the FP64 instantiation.
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,

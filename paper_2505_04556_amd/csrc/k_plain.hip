@@ -43,26 +43,17 @@ __device__ inline float square<float>(float d) { return d * d; }
 template <>
 __device__ inline double square<double>(float d) { return (double)d * (double)d; }
 
+// One work unit: tile chunk `chunk` of the triangle for the LANES permutations
+// of group `pg`; writes partial[chunk * P_pad + pg * LANES + lane].
 template <int T, int LANES, typename Acc>
-__global__ __launch_bounds__(LANES) void k_plain(
-    const float *__restrict__ mat, int64_t n, int64_t nt, int64_t n_tiles,
-    int64_t tiles_per_chunk, int64_t pgroups, int64_t grid_real,
-    const uint16_t *__restrict__ lab, int64_t P_pad, const double *__restrict__ w, int32_t k,
-    double *__restrict__ partial) {
-    // Blocks are dealt to the 8 XCDs round-robin; map them so that consecutive
-    // logical blocks (the permutation groups of one tile chunk) share an XCD
-    // and therefore its L2.
-    const int64_t gpad = gridDim.x;
-    const int64_t bid = blockIdx.x;
-    const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
-    if (logical >= grid_real) return;
-    const int64_t pg = logical % pgroups;
-    const int64_t chunk = logical / pgroups;
+__device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int64_t nt,
+                                  int64_t n_tiles, int64_t tiles_per_chunk,
+                                  const uint16_t *__restrict__ lab, int64_t P_pad,
+                                  const double *__restrict__ w, int32_t k,
+                                  double *__restrict__ partial, int64_t chunk, int64_t pg,
+                                  Acc (&sD)[T][T], double (&sWt)[kWeightCache]) {
     const int tid = threadIdx.x;
     const int64_t perm = pg * LANES + tid;
-
-    __shared__ Acc sD[T][T];
-    __shared__ double sWt[kWeightCache];
     const int kc = k < kWeightCache ? k : kWeightCache;
     for (int g = tid; g < kc; g += LANES) sWt[g] = w[g];
 
@@ -76,7 +67,6 @@ __global__ __launch_bounds__(LANES) void k_plain(
         constexpr int kPer = T * T / LANES;  // staged elements per thread
         static_assert(kPer >= 1 && (T * T) % LANES == 0, "tile/lane shape");
         float pre[kPer];
-        // Prefetch the first tile.
         auto fetch = [&](int64_t I_, int64_t J_) {
             const int64_t i0 = I_ * T, j0 = J_ * T;
 #pragma unroll
@@ -123,11 +113,48 @@ __global__ __launch_bounds__(LANES) void k_plain(
     partial[chunk * P_pad + perm] = tot;
 }
 
+// Blocks are dealt to the 8 XCDs round-robin; map them so that consecutive
+// logical blocks (the permutation groups of one tile chunk) share an XCD and
+// therefore its L2.
+__device__ inline int64_t xcd_logical(int64_t bid, int64_t gpad) {
+    return (bid & 7) * (gpad >> 3) + (bid >> 3);
+}
+
+template <int T, int LANES, typename Acc>
+__global__ __launch_bounds__(LANES) void k_plain(
+    const float *__restrict__ mat, int64_t n, int64_t nt, int64_t n_tiles,
+    int64_t tiles_per_chunk, int64_t pgroups, int64_t grid_real,
+    const uint16_t *__restrict__ lab, int64_t P_pad, const double *__restrict__ w, int32_t k,
+    double *__restrict__ partial) {
+    const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
+    if (logical >= grid_real) return;
+    __shared__ Acc sD[T][T];
+    __shared__ double sWt[kWeightCache];
+    plain_unit<T, LANES, Acc>(mat, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
+                              logical / pgroups, logical % pgroups, sD, sWt);
+}
+
+// Work-list form: block b runs unit units[b] = (job, chunk, pgroup) of the
+// job table, so one launch can mix units of many independent problems.
+__global__ __launch_bounds__(kServeLanes) void k_plain_worklist(
+    const JobDesc *__restrict__ jobs, const UnitDesc *__restrict__ units,
+    const int32_t *__restrict__ count) {
+    const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
+    if (logical >= *count) return;
+    const UnitDesc u = units[logical];
+    const JobDesc j = jobs[u.job];
+    __shared__ float sD[kServeTile][kServeTile];
+    __shared__ double sWt[kWeightCache];
+    plain_unit<kServeTile, kServeLanes, float>(j.mat, j.n, j.nt, j.n_tiles, j.tiles_per_chunk,
+                                               j.lab, j.P_pad, j.w, j.k, j.partial, u.chunk,
+                                               u.pgroup, sD, sWt);
+}
+
 template <int T, int LANES, typename Acc>
 void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t *lab,
                 const double *w, int32_t k, double *partial, hipStream_t s) {
     const int64_t grid_real = pl.chunks * pl.pgroups;
-    const int64_t gpad = round_up(grid_real, 8);
+    const int64_t gpad = round_up(grid_real, 8);  // xcd_logical needs a multiple of 8
     hipLaunchKernelGGL((k_plain<T, LANES, Acc>), dim3((unsigned)gpad), dim3(LANES), 0, s, mat,
                        n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups, grid_real, lab,
                        pl.P_pad, w, k, partial);
@@ -172,6 +199,13 @@ int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
     PSTAT_PLAIN_CASE(64, 256)
 #undef PSTAT_PLAIN_CASE
     return -1;
+}
+
+void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
+                           int64_t max_units, hipStream_t s) {
+    const int64_t gpad = round_up(max_units > 0 ? max_units : 1, 8);
+    hipLaunchKernelGGL(k_plain_worklist, dim3((unsigned)gpad), dim3(kServeLanes), 0, s, jobs, units,
+                       count);
 }
 
 } // namespace pstat

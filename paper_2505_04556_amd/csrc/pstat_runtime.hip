@@ -10,48 +10,12 @@
 #include <vector>
 
 #include "../../include/pstat.h"
-#include "internal.h"
+#include "runtime.h"
 
-using namespace pstat;
+namespace pstat {
+namespace rt {
 
-namespace {
-
-constexpr int kVersion = 10000;  // 1.0.0
-
-struct Tuning {
-    int tile = 0;
-    int batch = 0;
-};
-
-struct DeviceInfo {
-    bool ready = false;
-    int n_cu = 256;
-    size_t lds_limit = 65536;
-};
-
-struct Thread {
-    int device = -1;
-    hipStream_t stream = nullptr;
-    int path = PSTAT_PATH_AUTO;
-    Tuning tuning[PSTAT_N_PATHS];
-    void *ws_user = nullptr;
-    size_t ws_user_bytes = 0;
-    // library-managed workspace (per thread, per device in use)
-    void *ws_own = nullptr;
-    size_t ws_own_bytes = 0;
-    int ws_own_device = -1;
-    // small device scalars: [0] label error flag (sticky for pstat_sW_k),
-    // [1] max label, [2] tie count
-    int32_t *flags = nullptr;
-    int flags_device = -1;
-    int32_t *host_flags = nullptr;  // pinned
-    // main-kernel timing (pstat_profile)
-    bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    char err[512] = {0};
-};
-
-thread_local Thread tls;
+thread_local Thread tls;  // declared in runtime.h
 
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_devices;
@@ -79,11 +43,6 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(PSTAT_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                      \
-    do {                                                   \
-        hipError_t e_ = (expr);                            \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
-    } while (0)
 
 int check_launch(const char *what) {
     hipError_t e = hipGetLastError();
@@ -115,19 +74,6 @@ int check_dev_ptr(const void *p, const char *name) {
     return PSTAT_OK;
 }
 
-// ---- workspace carving --------------------------------------------------------
-struct Carver {
-    char *base;
-    size_t cap;
-    size_t used = 0;
-    bool dry;  // size-only pass
-    void *take(size_t bytes) {
-        used = (used + 255) & ~(size_t)255;
-        void *p = dry ? nullptr : base + used;
-        used += bytes;
-        return p;
-    }
-};
 
 int acquire_workspace(size_t bytes, char **out) {
     if (tls.ws_user) {
@@ -175,11 +121,14 @@ int mfma_dtype(int path) {
     return path == PSTAT_PATH_MFMA_BF16 ? 0 : path == PSTAT_PATH_MFMA_F16 ? 1 : 2;
 }
 
-// The tuned default path and parameters for a shape (the autotuner's table is
-// applied by the Python layer through pstat_set_path / pstat_set_tuning).
-int resolve_path(int path) {
+// Default form for a shape when the thread asked for PSTAT_PATH_AUTO (the
+// autotuner's per-shape choices are applied through pstat_set_path): the MFMA
+// contraction costs 4k flops per pair-permutation in split BF16 against about
+// three VALU operations for the plain kernel at 1/64 of the matrix-core rate,
+// so it wins while k stays small; tiny matrices stay on the plain kernel.
+int resolve_path(int path, int64_t n, int32_t k) {
     if (path != PSTAT_PATH_AUTO) return path;
-    return PSTAT_PATH_PLAIN_F32;
+    return (n >= 512 && k <= 16) ? PSTAT_PATH_MFMA_SPLIT_BF16 : PSTAT_PATH_PLAIN_F32;
 }
 
 void plain_params(int path, int64_t P, int *tile, int *lanes) {
@@ -196,21 +145,6 @@ void mfma_params(int path, int *kchunk_cols, int *ncols) {
     *kchunk_cols = t.tile;   // 0 = planner's choice
     *ncols = t.batch ? t.batch : 512;
 }
-
-// ---- s_W on a staged problem ------------------------------------------------
-// Scratch of one s_W evaluation of P permutations on the given path.
-struct SwLayout {
-    int path = 0;
-    uint8_t *bad = nullptr;      // per-permutation "had a bad label" flags
-    uint16_t *lab = nullptr;     // staged labels
-    double *partial = nullptr;   // plain: [chunks][P_pad]
-    void *tiles = nullptr;       // MFMA: pre-squared tiles (unless registered)
-    int32_t *tab = nullptr;      // MFMA: work-item table
-    float *z = nullptr;          // MFMA: [items][P][k]
-    double *tmp = nullptr;       // MFMA: [P][k]
-    PlainPlan pp{};
-    MfmaPlan mp{};
-};
 
 void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
                SwLayout &L) {
@@ -259,29 +193,10 @@ size_t plain_bytes_bound(int64_t n, int64_t P, int path) {
 // rows[q] of g, or row q when rows is NULL; rows is only used by plain paths),
 // run the kernel, reduce into out[0..P).  tiles: pre-squared tiles of a
 // registered matrix, or NULL to run the pre-pass into L.tiles.
-// Event pair around the main kernel when this thread is profiling.
-struct KernelTimer {
-    hipEvent_t a = nullptr, b = nullptr;
-    KernelTimer(hipStream_t s, bool timed) {
-        if (!tls.profiling || !timed) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-            (void)hipGetLastError();
-            a = b = nullptr;
-            return;
-        }
-        (void)hipEventRecord(a, s);
-    }
-    void stop(hipStream_t s) {
-        if (!a) return;
-        (void)hipEventRecord(b, s);
-        tls.events.emplace_back(a, b);
-        a = b = nullptr;
-    }
-};
 
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
-            double *out, const void *tiles, int32_t *err_flag, bool timed = true) {
+            double *out, const void *tiles, int32_t *err_flag, bool timed) {
     hipStream_t s = tls.stream;
     int rc;
     launch_fill_u8(L.bad, P, 0, s);
@@ -350,6 +265,7 @@ int sW_common(const float *mat, int64_t n, const int32_t *groupings, int64_t n_p
         if ((rc = scan_labels_sync(groupings, n_perms * n, kMaxGroups, &mx))) return rc;
         k = mx + 1;
     }
+    path = resolve_path(path, n, k);
     const size_t need = sW_bytes(n, n_perms, k, path, tiles == nullptr);
     char *ws;
     if ((rc = acquire_workspace(need, &ws))) return rc;
@@ -361,7 +277,7 @@ int sW_common(const float *mat, int64_t n, const int32_t *groupings, int64_t n_p
 
 int init_flags() {
     if (tls.flags && tls.flags_device == tls.device) return PSTAT_OK;
-    if (!tls.host_flags) HIP_TRY(hipHostMalloc((void **)&tls.host_flags, 64, hipHostMallocDefault));
+    if (!tls.host_flags) HIP_TRY(hipHostMalloc((void **)&tls.host_flags, 256, hipHostMallocDefault));
     if (tls.flags) (void)hipFree(tls.flags);
     HIP_TRY(hipMalloc((void **)&tls.flags, 64));
     HIP_TRY(hipMemset(tls.flags, 0, 64));
@@ -369,13 +285,95 @@ int init_flags() {
     return PSTAT_OK;
 }
 
-// Tie band of the p-value recheck: kBandMargin times the largest relative
-// error of the fast path over the observed grouping and the first
-// kBandSamples permutations (all recomputed in FP64).
-constexpr int64_t kBandSamples = 15;
-constexpr double kBandMargin = 16.0;
 
-} // namespace
+// ---- the whole permutation test in phases ------------------------------------
+void carve_head(Carver &c, int64_t n, int64_t R, int32_t k, TestHead &h) {
+    const int64_t nsT = sT_partials_count(n);
+    h.allg = (int32_t *)c.take((size_t)R * n * sizeof(int32_t));
+    h.w = (double *)c.take((size_t)k * sizeof(double));
+    h.counts = (uint32_t *)c.take((size_t)k * sizeof(uint32_t));
+    h.sw = (double *)c.take((size_t)R * sizeof(double));
+    h.sTp = (double *)c.take((size_t)(nsT + 1) * sizeof(double));
+    h.sT = h.sTp ? h.sTp + nsT : nullptr;
+    h.pv = (double *)c.take(sizeof(double));
+    h.list = (int32_t *)c.take((size_t)R * sizeof(int32_t));
+    h.vals = (double *)c.take((size_t)R * sizeof(double));
+    h.band = (double *)c.take(sizeof(double));
+    h.result = (double *)c.take(4 * sizeof(double));
+}
+
+int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t k,
+                 int64_t n_perms, uint64_t seed, int32_t max_label) {
+    hipStream_t s = tls.stream;
+    HIP_TRY(hipMemcpyAsync(h.allg, grouping, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    launch_permute(grouping, n, n_perms, seed, max_label, h.allg + n, dev_info().lds_limit, s);
+    int rc = check_launch("permute");
+    if (rc) return rc;
+    launch_group_weights(grouping, n, k, h.counts, h.w, s);
+    return check_launch("group weights");
+}
+
+int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
+                int path, char *region, size_t region_bytes, int64_t *rechecked_out) {
+    hipStream_t s = tls.stream;
+    int rc;
+    const int64_t R = n_perms + 1;
+    launch_sT(mat, n, h.sTp, h.sT, s);
+    if ((rc = check_launch("s_T"))) return rc;
+    // FP64 recheck.  First the observed grouping and the first few
+    // permutations: the observed value gives F_obs, and the largest relative
+    // error of the fast path over these samples sets the tie band.  Then every
+    // permutation whose fast s_W lies within the band of the observed value is
+    // recomputed, so that the p-value count is decided at FP64 accuracy.
+    int64_t rechecked = 0;
+    if (path != PSTAT_PATH_PLAIN_F64) {
+        const int64_t S = (n_perms < kBandSamples ? n_perms : kBandSamples) + 1;
+        launch_iota(h.list, S, s);
+        {
+            Carver c{region, region_bytes, 0, false};
+            SwLayout L;
+            layout_sW(c, n, S, k, PSTAT_PATH_PLAIN_F64, true, L);
+            if ((rc = exec_sW(L, mat, n, h.allg, h.list, S, k, k, h.w, h.vals, nullptr, tls.flags,
+                              false)))
+                return rc;
+        }
+        launch_tie_band(h.sw, h.vals, S, kBandMargin, h.band, s);
+        launch_scatter(h.vals, h.list, S, h.sw, s);
+        if ((rc = check_launch("tie band"))) return rc;
+        int64_t m = 0;
+        if (n_perms >= S) {
+            launch_fill_i32(tls.flags + 2, 1, 0, s);
+            launch_flag_ties(h.sw, S, R, h.band, h.list, tls.flags + 2, s);
+            if ((rc = check_launch("tie flags"))) return rc;
+            HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, 3 * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            m = tls.host_flags[2];
+        }
+        if (m > 0) {
+            Carver c{region, region_bytes, 0, false};
+            SwLayout L;
+            layout_sW(c, n, m, k, PSTAT_PATH_PLAIN_F64, true, L);
+            if ((rc = exec_sW(L, mat, n, h.allg, h.list, m, k, k, h.w, h.vals, nullptr, tls.flags,
+                              false)))
+                return rc;
+            launch_scatter(h.vals, h.list, m, h.sw, s);
+            if ((rc = check_launch("recheck scatter"))) return rc;
+        }
+        rechecked = S - 1 + m;
+    }
+    launch_pvalue(h.sw, h.sw + 1, n_perms, h.pv, s);
+    launch_pack_result(h.sw, h.sT, n, k, h.pv, h.result, s);
+    if ((rc = check_launch("result"))) return rc;
+    if (rechecked_out) *rechecked_out = rechecked;
+    return PSTAT_OK;
+}
+
+} // namespace rt
+} // namespace pstat
+
+using namespace pstat;
+using namespace pstat::rt;
 
 extern "C" {
 
@@ -457,19 +455,18 @@ size_t pstat_workspace_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int p
     if (n < 2 || n_perms < 0 || n_groups < 1 || n_groups > kMaxGroups) return 0;
     if (path != PSTAT_PATH_AUTO && (path < 0 || path >= PSTAT_N_PATHS)) return 0;
     if (tls.device < 0) return 0;
-    return sW_bytes(n, n_perms, n_groups, resolve_path(path), true);
+    return sW_bytes(n, n_perms, n_groups, resolve_path(path, n, n_groups), true);
 }
 
 int pstat_sW(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
              const double *inv_group_sizes, double *out) {
-    return sW_common(mat, n, groupings, n_perms, 0, inv_group_sizes, out, true, nullptr,
-                     resolve_path(tls.path));
+    return sW_common(mat, n, groupings, n_perms, 0, inv_group_sizes, out, true, nullptr, tls.path);
 }
 
 int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
                int32_t n_groups, const double *inv_group_sizes, double *out) {
     return sW_common(mat, n, groupings, n_perms, n_groups, inv_group_sizes, out, false, nullptr,
-                     resolve_path(tls.path));
+                     tls.path);
 }
 
 int pstat_check_labels(void) {
@@ -564,34 +561,16 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         (rc = check_dev_ptr(result, "result")))
         return rc;
     if (sW_all && (rc = check_dev_ptr(sW_all, "sW_all"))) return rc;
-    const int path = resolve_path(tls.path);
     const int32_t k = n_groups;
+    const int path = resolve_path(tls.path, n, k);
     hipStream_t s = tls.stream;
     int32_t max_label = -1;
     if ((rc = scan_labels_sync(grouping, n, k, &max_label))) return rc;
 
     const int64_t R = n_perms + 1;  // the observed grouping is row 0
-    const int64_t nsT = sT_partials_count(n);
-    // Head block (lives through the call), then region B, reused by the main
-    // evaluation and by the FP64 recheck.
-    auto carve_head = [&](Carver &c, int32_t *&allg, double *&w, uint32_t *&counts,
-                          double *&sw, double *&sTp, double *&pv, int32_t *&list,
-                          double *&vals, double *&band) {
-        allg = (int32_t *)c.take((size_t)R * n * sizeof(int32_t));
-        w = (double *)c.take((size_t)k * sizeof(double));
-        counts = (uint32_t *)c.take((size_t)k * sizeof(uint32_t));
-        sw = (double *)c.take((size_t)R * sizeof(double));
-        sTp = (double *)c.take((size_t)(nsT + 1) * sizeof(double));
-        pv = (double *)c.take(sizeof(double));
-        list = (int32_t *)c.take((size_t)R * sizeof(int32_t));
-        vals = (double *)c.take((size_t)R * sizeof(double));
-        band = (double *)c.take(sizeof(double));
-    };
-    int32_t *allg, *list;
-    double *w, *sw, *sTp, *pv, *vals, *band;
-    uint32_t *counts;
+    TestHead h;
     Carver dry{nullptr, 0, 0, true};
-    carve_head(dry, allg, w, counts, sw, sTp, pv, list, vals, band);
+    carve_head(dry, n, R, k, h);
     const size_t head = dry.used + 256;
     size_t region = sW_bytes(n, R, k, path, true);
     const size_t region64 = plain_bytes_bound(n, R, PSTAT_PATH_PLAIN_F64);
@@ -599,67 +578,21 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     char *ws;
     if ((rc = acquire_workspace(head + region, &ws))) return rc;
     Carver hc{ws, head, 0, false};
-    carve_head(hc, allg, w, counts, sw, sTp, pv, list, vals, band);
-    double *sT = sTp + nsT;
-    if (sW_all) sw = sW_all;
+    carve_head(hc, n, R, k, h);
+    if (sW_all) h.sw = sW_all;
+    if (result) h.result = result;
 
-    HIP_TRY(hipMemcpyAsync(allg, grouping, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    launch_permute(grouping, n, n_perms, seed, max_label, allg + n, dev_info().lds_limit, s);
-    if ((rc = check_launch("permute"))) return rc;
-    launch_group_weights(grouping, n, k, counts, w, s);
-    if ((rc = check_launch("group weights"))) return rc;
+    if ((rc = prepare_test(h, n, grouping, k, n_perms, seed, max_label))) return rc;
     {
         Carver c{ws + head, region, 0, false};
         SwLayout L;
         layout_sW(c, n, R, k, path, true, L);
-        if ((rc = exec_sW(L, mat, n, allg, nullptr, R, k, k, w, sw, nullptr, tls.flags))) return rc;
+        if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags)))
+            return rc;
     }
-    launch_sT(mat, n, sTp, sT, s);
-    if ((rc = check_launch("s_T"))) return rc;
-
-    // FP64 recheck.  First the observed grouping and the first few
-    // permutations: the observed value gives F_obs, and the largest relative
-    // error of the fast path over these samples sets the tie band.  Then every
-    // permutation whose fast s_W lies within the band of the observed value is
-    // recomputed, so that the p-value count is decided at FP64 accuracy.
     int64_t rechecked = 0;
-    if (path != PSTAT_PATH_PLAIN_F64) {
-        const int64_t S = (n_perms < kBandSamples ? n_perms : kBandSamples) + 1;
-        launch_iota(list, S, s);
-        {
-            Carver c{ws + head, region, 0, false};
-            SwLayout L;
-            layout_sW(c, n, S, k, PSTAT_PATH_PLAIN_F64, true, L);
-            if ((rc = exec_sW(L, mat, n, allg, list, S, k, k, w, vals, nullptr, tls.flags, false)))
-                return rc;
-        }
-        launch_tie_band(sw, vals, S, kBandMargin, band, s);
-        launch_scatter(vals, list, S, sw, s);
-        if ((rc = check_launch("tie band"))) return rc;
-        int64_t m = 0;
-        if (n_perms >= S) {
-            launch_fill_i32(tls.flags + 2, 1, 0, s);
-            launch_flag_ties(sw, S, R, band, list, tls.flags + 2, s);
-            if ((rc = check_launch("tie flags"))) return rc;
-            HIP_TRY(hipMemcpyAsync(tls.host_flags, tls.flags, 3 * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            m = tls.host_flags[2];
-        }
-        if (m > 0) {
-            Carver c{ws + head, region, 0, false};
-            SwLayout L;
-            layout_sW(c, n, m, k, PSTAT_PATH_PLAIN_F64, true, L);
-            if ((rc = exec_sW(L, mat, n, allg, list, m, k, k, w, vals, nullptr, tls.flags, false)))
-                return rc;
-            launch_scatter(vals, list, m, sw, s);
-            if ((rc = check_launch("recheck scatter"))) return rc;
-        }
-        rechecked = S - 1 + m;
-    }
-    launch_pvalue(sw, sw + 1, n_perms, pv, s);
-    launch_pack_result(sw, sT, n, k, pv, result, s);
-    if ((rc = check_launch("result"))) return rc;
+    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head, region, &rechecked))) return rc;
+    (void)s;
     if (n_rechecked) *n_rechecked = rechecked;
     return PSTAT_OK;
 }
@@ -670,7 +603,7 @@ int pstat_matrix_register(const float *mat, int64_t n, int path, int64_t *handle
     if (!handle) return fail(PSTAT_EINVAL, "handle is NULL");
     if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2");
     if ((rc = check_dev_ptr(mat, "mat"))) return rc;
-    path = resolve_path(path);
+    if (path == PSTAT_PATH_AUTO) path = PSTAT_PATH_MFMA_SPLIT_BF16;
     if (path < 0 || path >= PSTAT_N_PATHS) return fail(PSTAT_EINVAL, "unknown path %d", path);
     void *tiles = nullptr;
     if (is_mfma(path)) {

@@ -1,0 +1,82 @@
+"""Serving on the GPU: continuous batching of several permutation tests whose
+work shares launches; every result must be bit-identical alone and in the mix,
+equal to the whole-test call on the same form, and match the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import load_pstat, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def requests(device_gen=True):
+    from paper_2505_04556_amd.serve import Request
+    import synth.device as sd
+    specs = [(600, [100, 200, 300], 199), (1000, [500, 500], 511), (1500, [300, 500, 700], 299),
+             (800, [100, 150, 250, 300], 399), (1200, [600, 600], 255), (700, [350, 350], 1023)]
+    reqs = []
+    for i, (n, sizes, P) in enumerate(specs):
+        base = synth.base_labels(sizes)
+        reqs.append(Request(id=i, n=n, k=len(sizes), grouping=base, n_perms=P, seed=7000 + i,
+                            arrival=0.004 * i,
+                            make_matrix=(lambda dev, n=n, s=6000 + i: sd.uniform_matrix(n, s, dev))))
+    return reqs
+
+
+@pytest.fixture(scope="module")
+def ps(dev):
+    return load_pstat()
+
+
+def serve(reqs, budget=8 << 30, round_work=2e9):
+    from paper_2505_04556_amd.serve import GpuExecutor, Server
+    ex = GpuExecutor(max_jobs=16, max_units=4096)
+    try:
+        srv = Server(ex, hbm_budget=budget, keep_sW=True, round_work=round_work, max_units=4096)
+        return srv.run(reqs), srv
+    finally:
+        ex.close()
+
+
+def test_mix_equals_alone_and_oracle(ps):
+    import torch
+    reqs = requests()
+    mixed, srv = serve(reqs)
+    assert mixed["stats"]["completed"] == len(reqs)
+    # work of several jobs shared rounds
+    assert max(jobs for _, _, jobs in srv.log) >= 2
+    for r in reqs:
+        alone, _ = serve([r])
+        a = alone["outcomes"][r.id]
+        m = mixed["outcomes"][r.id]
+        assert a.result == m.result, r.id
+        assert np.array_equal(a.sW_all, m.sW_all), r.id
+        # same numbers as the whole-test entry point on the plain FP32 form
+        ps.pstat_set_path("plain_f32")
+        D = r.make_matrix(torch.device("cuda"))
+        sw = torch.empty(r.n_perms + 1, dtype=torch.float64, device="cuda")
+        res, _ = ps.pstat_permanova(D, torch.from_numpy(r.grouping).cuda(), r.k, r.n_perms,
+                                    r.seed, sW_all=sw)
+        assert np.array_equal(sw.cpu().numpy(), m.sW_all), r.id
+        assert list(res.cpu().numpy()) == m.result, r.id
+        # and the FP64 oracle
+        ref = oracle.permanova(D.cpu().numpy(), r.grouping, r.n_perms, r.seed)
+        assert max_rel(m.sW_all[1:], ref["sW_perm"]) <= 1e-5
+        assert abs(m.result[0] - ref["F_obs"]) <= 1e-5 * abs(ref["F_obs"])
+        assert m.result[1] == ref["p"]
+
+
+def test_admission_under_a_small_budget(ps):
+    reqs = requests()
+    from paper_2505_04556_amd.serve import GpuExecutor
+    ex = GpuExecutor(max_jobs=4, max_units=512)
+    try:
+        fps = [ex.footprint(r) for r in reqs]
+    finally:
+        ex.close()
+    budget = int(max(fps) * 1.5)            # at most one or two tests resident
+    res, _ = serve(reqs, budget=budget)
+    assert res["stats"]["completed"] == len(reqs)
+    assert res["peak_bytes"] <= budget
