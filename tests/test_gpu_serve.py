@@ -20,7 +20,7 @@ def requests(device_gen=True):
     for i, (n, sizes, P) in enumerate(specs):
         base = synth.base_labels(sizes)
         reqs.append(Request(id=i, n=n, k=len(sizes), grouping=base, n_perms=P, seed=7000 + i,
-                            arrival=0.004 * i,
+                            arrival=0.0,
                             make_matrix=(lambda dev, n=n, s=6000 + i: sd.uniform_matrix(n, s, dev))))
     return reqs
 
@@ -30,7 +30,7 @@ def ps(dev):
     return load_pstat()
 
 
-def serve(reqs, budget=8 << 30, round_work=2e9):
+def serve(reqs, budget=8 << 30, round_work=1e8):
     from paper_2505_04556_amd.serve import GpuExecutor, Server
     ex = GpuExecutor(max_jobs=16, max_units=4096)
     try:
@@ -45,8 +45,9 @@ def test_mix_equals_alone_and_oracle(ps):
     reqs = requests()
     mixed, srv = serve(reqs)
     assert mixed["stats"]["completed"] == len(reqs)
-    # work of several jobs shared rounds
+    # rounds carried work of several jobs (small rounds: every job spans several)
     assert max(jobs for _, _, jobs in srv.log) >= 2
+    assert srv.log and len(srv.log) > len(reqs)
     for r in reqs:
         alone, _ = serve([r])
         a = alone["outcomes"][r.id]
