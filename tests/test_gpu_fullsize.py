@@ -1,0 +1,171 @@
+"""Parity at the full workloads, in the launch configuration bench.py times
+(pstat_permanova with the default tuning):
+
+* n = 10,000 (Euclidean, k = 5, 9,999 permutations): every s_W against the
+  FP64 oracle, F_obs, and the p-value (identical); every s_W also against the
+  Euclidean closed form computed from the points.
+* n = 25,000 (Euclidean, k = 10 uneven groups, 3,999 permutations): every
+  computation form against the oracle on all permutations -- the per-dtype
+  precision table -- and p identical for the forms that meet 1e-5.
+* n = 100,000 (40 GB matrix, k = 3, 999 permutations): 64-bit offsets; sampled
+  permutations against the oracle fed by row blocks copied from the device,
+  F_obs against the oracle, and the p-value consistent with the returned s_W.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, load_pstat, max_rel
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def ps(dev):
+    return load_pstat()
+
+
+def record(name, payload):
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, f"fullsize_{name}.json"), "w") as f:
+            json.dump(payload, f, indent=1)
+    print(name, json.dumps(payload), flush=True)
+
+
+def whole_test(ps, D, cfg, path):
+    import torch
+    ps.pstat_set_path(path)
+    base = torch.from_numpy(synth.base_labels(cfg["sizes"])).cuda()
+    P = cfg["n_perms"]
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rech = ps.pstat_permanova(D, base, cfg["k"], P, cfg["perm_seed"], sW_all=sw)
+    torch.cuda.synchronize()
+    return res.cpu().numpy(), sw.cpu().numpy(), rech
+
+
+def huygens(points, labels, scale):
+    """Closed form of s_W for Euclidean distances: sum over groups of the
+    squared deviations from the group mean, for every row of labels."""
+    x = points
+    sq = (x * x).sum(1)
+    out = np.zeros(labels.shape[0])
+    for g in range(int(labels.max()) + 1):
+        M = (labels == g).astype(np.float64)
+        ng = M.sum(1)
+        sx = M @ x
+        out += (M @ sq) - (sx * sx).sum(1) / ng
+    return out / (scale * scale)
+
+
+def test_n10000_all_permutations(ps):
+    import synth.device as sd
+    cfg = synth.config(1)
+    D = sd.matrix(cfg)
+    Dh = D.cpu().numpy()
+    base = synth.base_labels(cfg["sizes"])
+    t0 = time.perf_counter()
+    ref = oracle.permanova(Dh, base, cfg["n_perms"], cfg["perm_seed"])
+    t_oracle = time.perf_counter() - t0
+    import torch
+    x = synth.euclid_points(cfg["n"], cfg["matrix_seed"])
+    assert float(np.max(Dh)) == 1.0   # entries are d / dmax
+    # dmax of the points (the generator's scale), for the closed form; on the
+    # host (torch's device cdist returned a wrong maximum at this size)
+    xt = torch.from_numpy(x)
+    scale = float(torch.cdist(xt, xt, compute_mode="donot_use_mm_for_euclid_dist").max())
+    del xt
+    closed = huygens(x, np.vstack([base, ref["perms"]]), scale)
+    assert max_rel(np.concatenate([[ref["sW_obs"]], ref["sW_perm"]]), closed) < 2e-7
+    rows = {}
+    for path in ("plain_f32", "mfma_split_bf16"):
+        res, sw, rech = whole_test(ps, D, cfg, path)
+        e_sw = max_rel(sw[1:], ref["sW_perm"])
+        e_F = abs(res[0] - ref["F_obs"]) / abs(ref["F_obs"])
+        rows[path] = dict(max_rel_sW=e_sw, rel_F_obs=e_F, p=res[1],
+                          p_oracle=ref["p"], rechecked=rech,
+                          max_rel_vs_closed_form=max_rel(sw, closed))
+        assert e_sw <= 1e-5, (path, e_sw)
+        assert e_F <= 1e-5, (path, e_F)
+        assert res[1] == ref["p"], (path, res[1], ref["p"])
+        assert max_rel(sw, closed) < 2e-7
+    record("n10000", dict(oracle_seconds=t_oracle, forms=rows, F_obs=ref["F_obs"], p=ref["p"]))
+
+
+def test_n25000_precision_table(ps):
+    import synth.device as sd
+    cfg = synth.config(2)
+    D = sd.matrix(cfg)
+    Dh = D.cpu().numpy()
+    base = synth.base_labels(cfg["sizes"])
+    t0 = time.perf_counter()
+    ref = oracle.permanova(Dh, base, cfg["n_perms"], cfg["perm_seed"])
+    t_oracle = time.perf_counter() - t0
+    del Dh
+    n, k = cfg["n"], cfg["k"]
+    kappa = ref["sT"] / (ref["sT"] - ref["sW_obs"])
+    table = {}
+    for path in ("plain_f32", "mfma_split_bf16", "mfma_f16", "mfma_bf16"):
+        res, sw, rech = whole_test(ps, D, cfg, path)
+        # the form's own s_W before any FP64 recheck: pstat_sW_k on the same groupings
+        import torch
+        g = torch.from_numpy(np.vstack([base, ref["perms"]])).cuda()
+        w = torch.from_numpy(synth.inv_group_sizes(cfg["sizes"])).cuda()
+        raw = ps.pstat_sW_k(D, g, k, w).cpu().numpy()
+        oracle_all = np.concatenate([[ref["sW_obs"]], ref["sW_perm"]])
+        F_raw = oracle.F(raw[:1], ref["sT"], n, k)[0]
+        table[path] = dict(max_rel_sW=max_rel(raw, oracle_all),
+                           mean_rel_sW=float(np.mean(np.abs(raw - oracle_all) / oracle_all)),
+                           rel_F_obs_form_only=abs(F_raw - ref["F_obs"]) / abs(ref["F_obs"]),
+                           rel_F_obs_after_recheck=abs(res[0] - ref["F_obs"]) / abs(ref["F_obs"]),
+                           p=res[1], p_identical=bool(res[1] == ref["p"]), rechecked=rech)
+        assert max_rel(raw, oracle_all) <= TOL[path], (path, table[path])
+        assert abs(res[0] - ref["F_obs"]) <= 1e-5 * abs(ref["F_obs"])
+        assert res[1] == ref["p"], (path, res[1], ref["p"])
+    record("n25000", dict(oracle_seconds=t_oracle, kappa_obs=kappa, F_obs=ref["F_obs"],
+                          p=ref["p"], forms=table))
+
+
+def test_n100000_sampled(ps):
+    import torch
+
+    import synth.device as sd
+    cfg = synth.config(3)
+    n, k, P = cfg["n"], cfg["k"], cfg["n_perms"]
+    D = sd.uniform_matrix(n, cfg["matrix_seed"])          # 40 GB, 64-bit offsets
+    base = synth.base_labels(cfg["sizes"])
+    perms = oracle.permute(base, P, cfg["perm_seed"])
+    sample = [0, 1, 2, 3, 250, 500, 750, P - 1]           # permutation indices
+    rows = np.vstack([base, perms[sample]])
+    w = synth.inv_group_sizes(cfg["sizes"])
+    acc = np.zeros(rows.shape[0])
+    sq = 0.0
+    block = 1000
+    host = torch.empty((block, n), dtype=torch.float32, pin_memory=True)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        host[: r1 - r0].copy_(D[r0:r1])
+        blk = host[: r1 - r0].numpy()
+        oracle.sW_rows(blk, r0, n, rows, w, acc)
+        sq = oracle.sq_rows(blk, r0, n, sq)
+    sT = sq / n
+    F_obs = oracle.F(acc[:1], sT, n, k)[0]
+    out = {}
+    for path in ("mfma_split_bf16", "plain_f32"):
+        res, sw, rech = whole_test(ps, D, cfg, path)
+        got = np.concatenate([sw[:1], sw[1:][sample]])
+        out[path] = dict(max_rel_sW_sample=max_rel(got, acc),
+                         rel_F_obs=abs(res[0] - F_obs) / abs(F_obs), rechecked=rech, p=res[1])
+        assert max_rel(got, acc) <= 1e-5, (path, out[path])
+        assert abs(res[0] - F_obs) <= 1e-5 * abs(F_obs)
+        # the oracle's s_T is one sequential FP64 sum of 5e9 terms: its own
+        # rounding is ~sqrt(5e9) * 2^-53 ~ 1e-11 relative
+        assert abs(res[3] - sT) <= 1e-10 * sT
+        # p is the count of the returned s_W at or below the observed one
+        assert res[1] == (1 + np.sum(sw[1:] <= sw[0])) / (1 + P)
+    record("n100000", dict(sample=sample, F_obs=F_obs, forms=out))
