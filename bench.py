@@ -105,6 +105,21 @@ def cpu_baseline(D_host, cfg, target_s=12.0):
                 perms_array=perms)
 
 
+def recorded_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(":", 1) for line in open(os.path.join(ROOT, summary))
+                      if ":" in line and not line.startswith("#"))
+        digest = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != digest:
+        return None
+    return float(fields["traffic_bytes_per_launch"].split()[0])
+
+
 def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
     """The serving trace: Poisson arrivals (4 requests/s), n in {1k..20k}, k in
     2..12 with Dirichlet sizes, 999 or 9,999 permutations; continuous batching
@@ -143,6 +158,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the permutation "
@@ -157,6 +174,14 @@ def main() -> int:
     import synth.device as sd
 
     ps = load()
+    if args.copy_probe_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = synth.config(args.config)
     n, k, P = cfg["n"], cfg["k"], cfg["n_perms"]
     log(f"workload {cfg['name']}: generating the matrix on the device")
@@ -205,8 +230,14 @@ def main() -> int:
         s = 2 if "split" in best else 1
         work = 2.0 * k * s * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12
+        traffic = None
+        if best == "mfma_split_bf16" and args.config == 1:
+            traffic = recorded_traffic("paper_2505_04556_amd/csrc/k_mfma.hip",
+                                       "profiles/k_mfma_split_n10000_hbm_traffic.txt")
         roof = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
+                    traffic_unit="HBM bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, "
+                                 "calibrated on a 1 GiB copy)",
                     kernel="k_mfma<2> (split-BF16)", kernel_ms=round(kern_ms, 4),
                     work_per_launch=f"{2 * k * s} flop x {pairs} pairs x {R} groupings")
     else:
