@@ -31,7 +31,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kPanel = 128;      // rows per panel
 constexpr int kKBlock = 64;      // columns per K block
@@ -126,21 +125,24 @@ __global__ void k_item_table(int64_t panels, int64_t kb_total, int64_t kchunk,
     }
 }
 
-// One-hot of 8 labels against g: 1.0 where label == g, else 0 (packed pairs).
+// One-hot of 8 labels against g: 1.0 where label == g, else 0, two 16-bit
+// lanes per dword: x = labels ^ (g, g) is 0 exactly where they match;
+// saturating (1, 1) - x is then 1 there and 0 elsewhere; times the bits of 1.0.
+// Written as packed 16-bit instructions (ALU only) so that each dword costs
+// three VALU operations.
 template <int DT>
 __device__ inline uint4 onehot8(uint4 L, uint32_t gg) {
-    const u16x2 one = {(unsigned short)One<DT>::v, (unsigned short)One<DT>::v};
-    const u16x2 neg = {(unsigned short)(0x10000u - One<DT>::v),
-                       (unsigned short)(0x10000u - One<DT>::v)};
-    const u16x2 uno = {1, 1};
+    const uint32_t one1 = 0x00010001u;
+    const uint32_t onev = One<DT>::v | (One<DT>::v << 16);
     uint32_t in[4] = {L.x, L.y, L.z, L.w};
     uint32_t out[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        const u16x2 x = __builtin_bit_cast(u16x2, in[q] ^ gg);
-        const u16x2 t = __builtin_elementwise_min(x, uno);  // 0 where equal, else 1
-        const u16x2 o = t * neg + one;                      // one - one * t (mod 2^16)
-        out[q] = __builtin_bit_cast(uint32_t, o);
+        const uint32_t x = in[q] ^ gg;
+        uint32_t t, o;
+        asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(t) : "v"(one1), "v"(x));
+        asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(o) : "v"(t), "v"(onev));
+        out[q] = o;
     }
     return make_uint4(out[0], out[1], out[2], out[3]);
 }

@@ -51,35 +51,64 @@ __device__ inline uint64_t stream_start(uint64_t seed, uint64_t p) {
     return mix64(seed ^ mix64(p + 1));
 }
 
+// The draw for the next step does not depend on the array, so it is taken
+// while the current step's two reads are in flight.
 template <typename E>
 __device__ inline void shuffle(E *a, int64_t n, uint64_t seed, int64_t p) {
+    if (n < 2) return;
     Stream st{stream_start(seed, (uint64_t)p)};
+    uint32_t j = st.below((uint32_t)n);
     for (int64_t i = n - 1; i >= 1; --i) {
-        const uint32_t j = st.below((uint32_t)(i + 1));
-        const E t = a[i];
-        a[i] = a[j];
-        a[j] = t;
+        const E ai = a[i];
+        const E aj = a[j];
+        const uint32_t jn = i > 1 ? st.below((uint32_t)i) : 0u;
+        a[i] = aj;
+        a[j] = ai;
+        j = jn;
     }
 }
 
 template <typename E>
 __global__ __launch_bounds__(64) void k_permute_lds(const int32_t *__restrict__ base, int64_t n,
                                                     int64_t P, uint64_t seed, int ppw,
-                                                    int32_t *__restrict__ out) {
+                                                    int vec, int32_t *__restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem[];
     E *arr = reinterpret_cast<E *>(smem);
     const int64_t p0 = (int64_t)blockIdx.x * ppw;
     const int tid = threadIdx.x;
     int live = ppw;
     if (p0 + live > P) live = (int)(P - p0);
-    for (int q = 0; q < live; q++)
-        for (int64_t i = tid; i < n; i += 64) arr[(int64_t)q * n + i] = (E)base[i];
+    // Copy in: each base label is loaded once (four per lane per load when
+    // base and every output row are 16-byte aligned: `vec`) and written into
+    // every permutation's slot.
+    const int64_t n4 = vec ? n / 4 : 0;
+    const int4 *base4 = reinterpret_cast<const int4 *>(base);
+    for (int64_t v = tid; v < n4; v += 64) {
+        const int4 b = base4[v];
+        for (int q = 0; q < live; q++) {
+            E *d = arr + (int64_t)q * n + 4 * v;
+            d[0] = (E)b.x;
+            d[1] = (E)b.y;
+            d[2] = (E)b.z;
+            d[3] = (E)b.w;
+        }
+    }
+    for (int64_t i = 4 * n4 + tid; i < n; i += 64) {
+        const E b = (E)base[i];
+        for (int q = 0; q < live; q++) arr[(int64_t)q * n + i] = b;
+    }
     __syncthreads();
     if (tid < live) shuffle<E>(arr + (int64_t)tid * n, n, seed, p0 + tid);
     __syncthreads();
-    for (int q = 0; q < live; q++)
-        for (int64_t i = tid; i < n; i += 64)
-            out[(p0 + q) * n + i] = (int32_t)arr[(int64_t)q * n + i];
+    // Copy out, 16-byte stores under the same condition.
+    for (int q = 0; q < live; q++) {
+        const E *src = arr + (int64_t)q * n;
+        int32_t *dst = out + (p0 + q) * n;
+        int4 *dst4 = reinterpret_cast<int4 *>(dst);
+        for (int64_t v = tid; v < n4; v += 64)
+            dst4[v] = make_int4(src[4 * v], src[4 * v + 1], src[4 * v + 2], src[4 * v + 3]);
+        for (int64_t i = 4 * n4 + tid; i < n; i += 64) dst[i] = (int32_t)src[i];
+    }
 }
 
 __global__ __launch_bounds__(64) void k_permute_global(const int32_t *__restrict__ base, int64_t n,
@@ -104,8 +133,9 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
     (void)hipFuncSetAttribute((const void *)k_permute_lds<E>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     const int64_t blocks = ceil_div(P, ppw);
+    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0) && ((uintptr_t)out % 16 == 0);
     hipLaunchKernelGGL(k_permute_lds<E>, dim3((unsigned)blocks), dim3(64), bytes, s, base, n, P,
-                       seed, (int)ppw, out);
+                       seed, (int)ppw, vec, out);
     return 0;
 }
 
