@@ -52,10 +52,25 @@ def load():
     return ps
 
 
-def time_path(ps, torch, path, D, base, cfg, steps, warmup):
+def autotuned(ps, torch, D, cfg, paths):
+    """Tile / permutations-per-batch (plain) and K-chunk / columns (MFMA) chosen
+    by the autotuner on this workload's own matrix and permutations."""
+    import synth
+    from paper_2505_04556_amd import autotune
+    base = torch.from_numpy(synth.base_labels(cfg["sizes"])).cuda()
+    perms = ps.pstat_permute(base, cfg["n_perms"], cfg["perm_seed"])
+    w = torch.from_numpy(synth.inv_group_sizes(cfg["sizes"])).cuda()
+    entry = autotune.tune(D, perms, cfg["k"], w, paths=paths, reps=2, cache={}, save=False)
+    del perms
+    return entry
+
+
+def time_path(ps, torch, path, D, base, cfg, steps, warmup, tuning=None):
     """Warm up, then time exactly `steps` whole tests; returns timings and the
     last step's outputs."""
     ps.pstat_set_path(path)
+    if tuning:
+        ps.pstat_set_tuning(path, tuning["tile"], tuning["batch"])
     n, k, P, seed = cfg["n"], cfg["k"], cfg["n_perms"], cfg["perm_seed"]
     sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
     res = torch.empty(4, dtype=torch.float64, device="cuda")
@@ -133,7 +148,11 @@ def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
                             n_perms=t["n_perms"], seed=t["perm_seed"], arrival=t["arrival"],
                             make_matrix=(lambda dev, n=t["n"], s=t["matrix_seed"]:
                                          sd.uniform_matrix(n, s, dev))))
-    ex = GpuExecutor(max_jobs=32, max_units=8192)
+    ex = GpuExecutor(max_jobs=32, max_units=8192, path="auto")
+    forms = {}
+    for r in reqs:
+        f = ex.form(r)
+        forms[f] = forms.get(f, 0) + 1
     try:
         srv = Server(ex, hbm_budget=budget_bytes, round_work=1.5e11, max_units=8192)
         res = srv.run(reqs)
@@ -144,7 +163,8 @@ def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
                  if o.error is None and o.admitted - o.arrival > 0.05)
     st.update(rounds=res["rounds"], peak_resident_GB=round(res["peak_bytes"] / 1e9, 3),
               budget_GB=round(budget_bytes / 1e9, 3), requests=count, arrivals_per_s=rate,
-              admissions_delayed_50ms=waited, quantiles="nearest rank", path="plain_f32 work-list")
+              admissions_delayed_50ms=waited, quantiles="nearest rank",
+              path="auto: work-list kernels of both forms in each round", jobs_by_form=forms)
     return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
 
 
@@ -157,6 +177,7 @@ def main() -> int:
     ap.add_argument("--paths", default="plain_f32,mfma_split_bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuning")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -191,10 +212,19 @@ def main() -> int:
     pairs = n * (n - 1) // 2
     pair_perms = pairs * P
 
+    paths = args.paths.split(",")
+    tuned = {}
+    if not args.no_tune:
+        log("autotuning " + ", ".join(paths))
+        entry = autotuned(ps, torch, D, cfg, tuple(paths))
+        tuned = {p: {"tile": v["tile"], "batch": v["batch"], "kernel_ms": round(v["kernel_ms"], 3)}
+                 for p, v in entry["paths"].items()}
+        log(f"  tuned: {tuned}")
     runs = {}
-    for path in args.paths.split(","):
+    for path in paths:
         log(f"timing {path}: {args.warmup} warm-up + {args.steps} steps")
-        runs[path] = time_path(ps, torch, path, D, base, cfg, args.steps, args.warmup)
+        runs[path] = time_path(ps, torch, path, D, base, cfg, args.steps, args.warmup,
+                               tuned.get(path))
         log(f"  {path}: {runs[path]['ms_per_step']:.2f} ms/step, "
             f"kernel {runs[path]['kernel_ms_total'] / max(1, runs[path]['kernel_launches']):.2f} ms")
 
@@ -270,6 +300,7 @@ def main() -> int:
                       "kernel_ms": round(v["kernel_ms_total"] / max(1, v["kernel_launches"]), 4),
                       "F_obs": float(v["result"][0]), "p": float(v["result"][1]),
                       "rechecked_perms": int(v["rechecked"]),
+                      "tuning": tuned.get(p),
                       "max_rel_err_vs_oracle_sample": acc.get(p)}
                   for p, v in runs.items()},
     }

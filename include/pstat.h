@@ -77,6 +77,11 @@ int pstat_set_stream(void *hip_stream);
  * PSTAT_PATH_AUTO (default) = the tuned choice for the problem shape. */
 int pstat_set_path(int path);
 
+/* The form PSTAT_PATH_AUTO stands for at n objects and n_groups groups (other
+ * paths are returned unchanged; PSTAT_EINVAL for an unknown path -- a resolved
+ * path is never negative).  Host only; needs no device. */
+int pstat_resolve_path(int path, int64_t n, int32_t n_groups);
+
 /* Tuning of one path for this thread: `tile` and `batch` override the tuned
  * values (0 = keep the tuned value).  Plain paths: tile = square tile edge
  * (32 or 64), batch = permutation lanes per work-group (64, 128 or 256).  MFMA
@@ -168,27 +173,30 @@ int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perm
 /* Not part of the paper's statement of the problem: the device side of a
  * serving loop that keeps several permutation tests resident and runs their
  * work in shared launches.  A job is one whole test (as pstat_permanova) on
- * the plain FP32 kernel with tile 32 and 256 permutation lanes; its work is
- * n_units units (one work-group each).  A round runs any list of units of any
- * live jobs in one launch of a work-list kernel, replayed from a captured
- * hipGraph (two graphs alternate, so a round's unit list can be filled while
- * the previous round runs).  A job's result depends only on its own units and
- * a fixed reduction order: it is bit-identical alone and in any mix. */
+ * the plain FP32 kernel (tile 32, 256 permutation lanes) or the split-BF16
+ * MFMA kernel (512 columns per work-group); its work is n_units units (one
+ * work-group each).  A round runs any list of units of any live jobs in one
+ * launch per form of the work-list kernels, replayed from a captured hipGraph
+ * (two graphs alternate, so a round's unit list can be filled while the
+ * previous round runs).  A job's result depends only on its own units and a
+ * fixed reduction order: it is bit-identical alone and in any mix. */
 
 /* Server with room for max_jobs live jobs and max_units units per round. */
 int pstat_serve_create(int64_t max_jobs, int64_t max_units, int64_t *server);
 /* Waits for its rounds, frees the server (job scratch stays the caller's). */
 int pstat_serve_destroy(int64_t server);
 
-/* Device scratch bytes one job needs (caller-owned, kept until release). */
-size_t pstat_job_bytes(int64_t n, int64_t n_perms, int32_t n_groups);
+/* Device scratch bytes one job needs (caller-owned, kept until release);
+ * path: PSTAT_PATH_PLAIN_F32, PSTAT_PATH_MFMA_SPLIT_BF16 or PSTAT_PATH_AUTO. */
+size_t pstat_job_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int path);
 
-/* Stage a test into `scratch`: validates `grouping` (SYNCHRONISES the stream),
- * weights, the n_perms shuffles of pstat_permute(seed), staged labels.  mat
+/* Stage a test into `scratch` for form `path` (as pstat_job_bytes): validates
+ * `grouping` (SYNCHRONISES the stream), weights, the n_perms shuffles of
+ * pstat_permute(seed), staged labels (and for MFMA the pre-squared tiles).  mat
  * must stay valid until release.  *job: the job's id; *n_units: its units,
  * numbered 0 .. n_units-1. */
 int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t *grouping,
-                     int32_t n_groups, int64_t n_perms, uint64_t seed, void *scratch,
+                     int32_t n_groups, int64_t n_perms, uint64_t seed, int path, void *scratch,
                      size_t scratch_bytes, int64_t *job, int64_t *n_units);
 
 /* Run `count` units (host array of (job, unit) pairs, 2*count int64) in one

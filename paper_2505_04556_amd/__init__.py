@@ -43,6 +43,7 @@ PATH_NAMES = {
     PSTAT_PATH_PLAIN_F64: "plain_f64",
 }
 PATH_IDS = {v: k for k, v in PATH_NAMES.items()}
+PATH_IDS["auto"] = PSTAT_PATH_AUTO
 
 _CODE_NAMES = {
     PSTAT_EINVAL: "EINVAL", PSTAT_ELABEL: "ELABEL", PSTAT_EDOMAIN: "EDOMAIN",
@@ -86,9 +87,10 @@ _SIGS = {
     "pstat_sW_registered": ([_i64, _P, _i64, _i32, _P, _P], _int),
     "pstat_serve_create": ([_i64, _i64, ctypes.POINTER(_i64)], _int),
     "pstat_serve_destroy": ([_i64], _int),
-    "pstat_job_bytes": ([_i64, _i64, _i32], _size),
-    "pstat_job_create": ([_i64, _P, _i64, _P, _i32, _i64, _u64, _P, _size, ctypes.POINTER(_i64),
-                          ctypes.POINTER(_i64)], _int),
+    "pstat_resolve_path": ([_int, _i64, _i32], _int),
+    "pstat_job_bytes": ([_i64, _i64, _i32, _int], _size),
+    "pstat_job_create": ([_i64, _P, _i64, _P, _i32, _i64, _u64, _int, _P, _size,
+                          ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _int),
     "pstat_serve_round": ([_i64, _P, _i64], _int),
     "pstat_job_finish": ([_i64, _i64, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(_i64)],
                          _int),
@@ -136,6 +138,18 @@ def pstat_set_path(path) -> None:
     p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(torch.device("cuda", torch.cuda.current_device()))
     _check(_lib.pstat_set_path(p))
+
+
+def pstat_resolve_path(path, n: int, n_groups: int) -> str:
+    """Name of the form `path` ("auto" included) runs at this shape; host only."""
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    r = int(_lib.pstat_resolve_path(p, int(n), int(n_groups)))
+    if r < 0:                       # a resolved path is never AUTO
+        _check(r)
+    return PATH_NAMES[r]
+
+
+resolve_path = pstat_resolve_path
 
 
 def pstat_set_tuning(path, tile: int = 0, batch: int = 0) -> None:
@@ -298,19 +312,22 @@ def pstat_serve_destroy(server: int) -> None:
     _check(_lib.pstat_serve_destroy(int(server)))
 
 
-def pstat_job_bytes(n: int, n_perms: int, n_groups: int) -> int:
+def pstat_job_bytes(n: int, n_perms: int, n_groups: int, path=PSTAT_PATH_PLAIN_F32) -> int:
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(torch.device("cuda", torch.cuda.current_device()))
-    return int(_lib.pstat_job_bytes(int(n), int(n_perms), int(n_groups)))
+    return int(_lib.pstat_job_bytes(int(n), int(n_perms), int(n_groups), p))
 
 
 def pstat_job_create(server: int, mat: torch.Tensor, grouping: torch.Tensor, n_groups: int,
-                     n_perms: int, seed: int, scratch: torch.Tensor) -> tuple[int, int]:
+                     n_perms: int, seed: int, scratch: torch.Tensor,
+                     path=PSTAT_PATH_PLAIN_F32) -> tuple[int, int]:
     """Returns (job id, number of work units)."""
+    p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(mat.device)
     job, units = _i64(0), _i64(0)
     _check(_lib.pstat_job_create(int(server), _dev(mat, torch.float32, "mat"), mat.shape[0],
                                  _dev(grouping, torch.int32, "grouping"), int(n_groups),
-                                 int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                 int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF, p,
                                  _dev(scratch, torch.uint8, "scratch"), scratch.numel(),
                                  ctypes.byref(job), ctypes.byref(units)))
     return int(job.value), int(units.value)

@@ -61,18 +61,27 @@ PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu);
 constexpr int kServeTile = 32;
 constexpr int kServeLanes = 256;
 struct JobDesc {              // one staged problem, device-resident
+    // plain form
     const float *mat;
     const uint16_t *lab;      // u16 [n_pad][P_pad], object-major
     const double *w;
     double *partial;          // [chunks][P_pad]
     int64_t n, nt, n_tiles, tiles_per_chunk, P_pad;
-    int32_t k, pad;
+    int32_t k, kind;          // kind: 0 plain FP32, 1 MFMA split BF16
+    // MFMA form (split BF16, 512 columns per work-group)
+    const void *tiles;        // pre-squared tiles
+    const uint16_t *lab_pm;   // u16 [P_pad_m][n_pad_m], permutation-major
+    const int32_t *tab;       // work-item table
+    float *z;                 // [items][R][k]
+    int64_t comp_units, kb_total, n_pad_m, R;
 };
-struct UnitDesc {             // one work-group's share of one job
-    int32_t job, chunk, pgroup;
-};
+struct UnitDesc {             // one work-group's share of one job: plain
+    int32_t job, chunk, pgroup;   // (tile chunk, permutation group); MFMA
+};                                // (work item, column block)
 void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                            int64_t max_units, hipStream_t s);
+void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
+                          int64_t max_units, hipStream_t s);
 // partial[chunk][P_pad] FP64 from u16 [n_pad][P_pad] labels.  Perm lane q of
 // the label table is permutation q.  f64 selects the FP64 instantiation.
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
@@ -99,6 +108,7 @@ size_t mfma_tile_bytes(int64_t n, int dtype);
 // Pre-pass: strict-upper d^2 of 128-row panels into MFMA fragment order.
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s);
 size_t mfma_table_bytes(const MfmaPlan &pl);
+void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);
 // z[item][P][k] FP32 sums of the (G^T U G) diagonal per (panel, K chunk) item;
 // tab is scratch for the item table (mfma_table_bytes).
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,

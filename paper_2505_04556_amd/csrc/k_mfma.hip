@@ -162,23 +162,15 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 // once per work-group in double-buffered LDS and read by all four waves; each
 // wave builds its own one-hot B fragments from u16 labels, one K step ahead.
 template <int DT, int NF>
-__global__ __launch_bounds__(256) void k_mfma(
-    const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
-    const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
-    const uint16_t *__restrict__ lab, int64_t n_pad, int32_t k, int64_t P,
-    float *__restrict__ z) {
+__device__ __attribute__((always_inline)) inline void mfma_unit(const uint4 *__restrict__ tiles, int64_t comp_units,
+                                 int64_t kb_total, const int32_t *__restrict__ tab, int64_t item,
+                                 int64_t nb, const uint16_t *__restrict__ lab, int64_t n_pad,
+                                 int32_t k, int64_t P, float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
     constexpr int NC = DT == 2 ? 2 : 1;     // A components (hi, lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
     constexpr int COLS = 4 * NF * 32;       // columns per work-group
     __shared__ uint4 sA[2][UNIT];
-
-    const int64_t gpad = gridDim.x;
-    const int64_t bid = blockIdx.x;
-    const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
-    if (logical >= grid_real) return;
-    const int64_t item = logical / nblocks;
-    const int64_t nb = logical % nblocks;
     const int64_t I = tab[3 * item], kb0 = tab[3 * item + 1], kb1 = tab[3 * item + 2];
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
@@ -285,6 +277,35 @@ __global__ __launch_bounds__(256) void k_mfma(
     }
 }
 
+template <int DT, int NF>
+__global__ __launch_bounds__(256) void k_mfma(
+    const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
+    const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
+    const uint16_t *__restrict__ lab, int64_t n_pad, int32_t k, int64_t P,
+    float *__restrict__ z) {
+    const int64_t gpad = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
+    if (logical >= grid_real) return;
+    mfma_unit<DT, NF>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
+                      lab, n_pad, k, P, z);
+}
+
+// Work-list form (serving): block b runs unit units[b] = (job, item, column
+// block) of a split-BF16 job in the job table.
+__global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict__ jobs,
+                                                      const UnitDesc *__restrict__ units,
+                                                      const int32_t *__restrict__ count) {
+    const int64_t gpad = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
+    if (logical >= *count) return;
+    const UnitDesc u = units[logical];
+    const JobDesc &j = jobs[u.job];
+    mfma_unit<2, 4>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk, u.pgroup,
+                    j.lab_pm, j.n_pad_m, j.k, j.R, j.z);
+}
+
 } // namespace
 
 size_t mfma_tile_bytes(int64_t n, int dtype) {
@@ -359,6 +380,16 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
     PSTAT_MFMA_CASE(2)
 #undef PSTAT_MFMA_CASE
     return -1;
+}
+
+void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
+                          int64_t max_units, hipStream_t s) {
+    const int64_t gpad = round_up(max_units > 0 ? max_units : 1, 8);
+    hipLaunchKernelGGL(k_mfma_worklist, dim3((unsigned)gpad), dim3(256), 0, s, jobs, units, count);
+}
+
+void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_item_table, dim3(1), dim3(64), 0, s, pl.panels, pl.kb_total, pl.kchunk, tab);
 }
 
 } // namespace pstat

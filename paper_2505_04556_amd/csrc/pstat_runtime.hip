@@ -415,6 +415,12 @@ int pstat_set_stream(void *hip_stream) {
     return PSTAT_OK;
 }
 
+int pstat_resolve_path(int path, int64_t n, int32_t n_groups) {
+    if (path < PSTAT_PATH_AUTO || path > PSTAT_PATH_PLAIN_F64)
+        return fail(PSTAT_EINVAL, "unknown path %d", path);
+    return resolve_path(path, n, n_groups);
+}
+
 int pstat_set_path(int path) {
     if (path != PSTAT_PATH_AUTO && (path < 0 || path >= PSTAT_N_PATHS))
         return fail(PSTAT_EINVAL, "unknown path %d", path);

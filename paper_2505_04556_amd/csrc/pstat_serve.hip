@@ -16,15 +16,20 @@ namespace {
 
 struct Job {
     bool live = false;
+    int kind = 0;                  // 0 plain FP32, 1 MFMA split BF16
     const float *mat = nullptr;
     int64_t n = 0, n_perms = 0;
     int32_t k = 0;
     TestHead head{};
     PlainPlan pl{};
+    MfmaPlan mp{};
     uint16_t *lab = nullptr;
     double *partial = nullptr;
+    float *z = nullptr;
+    double *tmp = nullptr;
     uint8_t *bad = nullptr;
     int64_t units = 0;
+    int64_t split = 1;             // units are (a, b) with b in [0, split)
 };
 
 struct Server {
@@ -32,9 +37,10 @@ struct Server {
     int64_t max_jobs = 0, max_units = 0;
     JobDesc *jobs_dev = nullptr;
     JobDesc *jobs_host = nullptr;           // pinned, one entry per slot
-    UnitDesc *units_dev[2] = {nullptr, nullptr};
-    int32_t *count_dev[2] = {nullptr, nullptr};
-    UnitDesc *units_host[2] = {nullptr, nullptr};  // pinned
+    // per alternating slot b: unit lists of the plain [0] and MFMA [1] kinds
+    UnitDesc *units_dev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int32_t *count_dev[2] = {nullptr, nullptr};    // [kind] counts of slot b
+    UnitDesc *units_host[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // pinned
     int32_t *count_host[2] = {nullptr, nullptr};   // pinned
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -57,19 +63,40 @@ Server *find_server(int64_t h) {
 // Scratch layout of one job inside the caller's buffer.
 struct JobLayout {
     TestHead head;
-    uint16_t *lab;
-    double *partial;
-    uint8_t *bad;
-    PlainPlan pl;
+    uint16_t *lab = nullptr;
+    double *partial = nullptr;
+    uint8_t *bad = nullptr;
+    PlainPlan pl{};
+    MfmaPlan mp{};
+    void *tiles = nullptr;
+    int32_t *tab = nullptr;
+    float *z = nullptr;
+    double *tmp = nullptr;
 };
 
-void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, JobLayout &L) {
+void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, int kind, JobLayout &L) {
     const int64_t R = n_perms + 1;
     carve_head(c, n, R, k, L.head);
-    L.pl = plain_plan(n, R, kServeTile, kServeLanes, dev_info().n_cu);
-    L.lab = (uint16_t *)c.take((size_t)L.pl.n_pad * L.pl.P_pad * sizeof(uint16_t));
-    L.partial = (double *)c.take((size_t)L.pl.chunks * L.pl.P_pad * sizeof(double));
     L.bad = (uint8_t *)c.take((size_t)R);
+    if (kind == 0) {
+        L.pl = plain_plan(n, R, kServeTile, kServeLanes, dev_info().n_cu);
+        L.lab = (uint16_t *)c.take((size_t)L.pl.n_pad * L.pl.P_pad * sizeof(uint16_t));
+        L.partial = (double *)c.take((size_t)L.pl.chunks * L.pl.P_pad * sizeof(double));
+        return;
+    }
+    L.mp = mfma_plan(n, R, k, 2, 0, 512, dev_info().n_cu);
+    L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
+    L.tiles = c.take(mfma_tile_bytes(n, 2));
+    L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
+    L.z = (float *)c.take((size_t)L.mp.items * R * k * sizeof(float));
+    L.tmp = (double *)c.take((size_t)R * k * sizeof(double));
+}
+
+int job_kind(int path, int64_t n, int32_t k) {
+    path = resolve_path(path, n, k);
+    if (path == PSTAT_PATH_PLAIN_F32) return 0;
+    if (path == PSTAT_PATH_MFMA_SPLIT_BF16) return 1;
+    return -1;
 }
 
 void destroy_server(Server *sv) {
@@ -77,9 +104,11 @@ void destroy_server(Server *sv) {
         if (sv->exec[b]) (void)hipGraphExecDestroy(sv->exec[b]);
         if (sv->graph[b]) (void)hipGraphDestroy(sv->graph[b]);
         if (sv->done[b]) (void)hipEventDestroy(sv->done[b]);
-        if (sv->units_dev[b]) (void)hipFree(sv->units_dev[b]);
+        for (int t = 0; t < 2; t++) {
+            if (sv->units_dev[b][t]) (void)hipFree(sv->units_dev[b][t]);
+            if (sv->units_host[b][t]) (void)hipHostFree(sv->units_host[b][t]);
+        }
         if (sv->count_dev[b]) (void)hipFree(sv->count_dev[b]);
-        if (sv->units_host[b]) (void)hipHostFree(sv->units_host[b]);
         if (sv->count_host[b]) (void)hipHostFree(sv->count_host[b]);
     }
     if (sv->jobs_dev) (void)hipFree(sv->jobs_dev);
@@ -119,17 +148,21 @@ int pstat_serve_create(int64_t max_jobs, int64_t max_units, int64_t *server) {
         return bail(e, "hipHostMalloc(job table)");
     memset(sv->jobs_host, 0, sizeof(JobDesc) * max_jobs);
     for (int b = 0; b < 2; b++) {
-        if ((e = hipMalloc((void **)&sv->units_dev[b], sizeof(UnitDesc) * max_units)) != hipSuccess)
-            return bail(e, "hipMalloc(units)");
+        for (int t = 0; t < 2; t++) {
+            if ((e = hipMalloc((void **)&sv->units_dev[b][t], sizeof(UnitDesc) * max_units)) !=
+                hipSuccess)
+                return bail(e, "hipMalloc(units)");
+            if ((e = hipHostMalloc((void **)&sv->units_host[b][t], sizeof(UnitDesc) * max_units,
+                                   hipHostMallocDefault)) != hipSuccess)
+                return bail(e, "hipHostMalloc(units)");
+            memset(sv->units_host[b][t], 0, sizeof(UnitDesc) * max_units);
+        }
         if ((e = hipMalloc((void **)&sv->count_dev[b], 64)) != hipSuccess)
             return bail(e, "hipMalloc(count)");
-        if ((e = hipHostMalloc((void **)&sv->units_host[b], sizeof(UnitDesc) * max_units,
-                               hipHostMallocDefault)) != hipSuccess)
-            return bail(e, "hipHostMalloc(units)");
         if ((e = hipHostMalloc((void **)&sv->count_host[b], 64, hipHostMallocDefault)) != hipSuccess)
             return bail(e, "hipHostMalloc(count)");
-        memset(sv->units_host[b], 0, sizeof(UnitDesc) * max_units);
         sv->count_host[b][0] = 0;
+        sv->count_host[b][1] = 0;
         if ((e = hipEventCreateWithFlags(&sv->done[b], hipEventDisableTiming)) != hipSuccess)
             return bail(e, "hipEventCreate");
     }
@@ -155,16 +188,18 @@ int pstat_serve_destroy(int64_t server) {
     return PSTAT_OK;
 }
 
-size_t pstat_job_bytes(int64_t n, int64_t n_perms, int32_t n_groups) {
+size_t pstat_job_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int path) {
     if (tls.device < 0 || n < 2 || n_perms < 0 || n_groups < 1 || n_groups > kMaxGroups) return 0;
+    const int kind = job_kind(path, n, n_groups);
+    if (kind < 0) return 0;
     Carver c{nullptr, 0, 0, true};
     JobLayout L;
-    layout_job(c, n, n_perms, n_groups, L);
+    layout_job(c, n, n_perms, n_groups, kind, L);
     return c.used + 256;
 }
 
 int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t *grouping,
-                     int32_t n_groups, int64_t n_perms, uint64_t seed, void *scratch,
+                     int32_t n_groups, int64_t n_perms, uint64_t seed, int path, void *scratch,
                      size_t scratch_bytes, int64_t *job, int64_t *n_units) {
     int rc = need_init();
     if (rc) return rc;
@@ -178,7 +213,9 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     if ((rc = check_dev_ptr(mat, "mat")) || (rc = check_dev_ptr(grouping, "grouping")) ||
         (rc = check_dev_ptr(scratch, "scratch")))
         return rc;
-    const size_t need = pstat_job_bytes(n, n_perms, n_groups);
+    const int kind = job_kind(path, n, n_groups);
+    if (kind < 0) return fail(PSTAT_EINVAL, "serving jobs run the plain FP32 or split-BF16 MFMA form");
+    const size_t need = pstat_job_bytes(n, n_perms, n_groups, path);
     if (scratch_bytes < need)
         return fail(PSTAT_ENOMEM, "job scratch of %zu bytes is smaller than the %zu needed",
                     scratch_bytes, need);
@@ -191,41 +228,66 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     if ((rc = scan_labels_sync(grouping, n, n_groups, &max_label))) return rc;
     Carver c{(char *)scratch, scratch_bytes, 0, false};
     JobLayout L;
-    layout_job(c, n, n_perms, n_groups, L);
+    layout_job(c, n, n_perms, n_groups, kind, L);
     const int64_t R = n_perms + 1;
     if ((rc = prepare_test(L.head, n, grouping, n_groups, n_perms, seed, max_label))) return rc;
     hipStream_t s = tls.stream;
     launch_fill_u8(L.bad, R, 0, s);
-    launch_stage_labels_om(L.head.allg, nullptr, n, R, L.pl.n_pad, L.pl.P_pad, n_groups, L.lab,
-                           L.bad, tls.flags, s);
-    if ((rc = check_launch("job label staging"))) return rc;
-
     JobDesc &d = sv->jobs_host[slot];
+    memset(&d, 0, sizeof(JobDesc));
     d.mat = mat;
-    d.lab = L.lab;
     d.w = L.head.w;
-    d.partial = L.partial;
     d.n = n;
-    d.nt = L.pl.n_t;
-    d.n_tiles = L.pl.n_tiles;
-    d.tiles_per_chunk = L.pl.tiles_per_chunk;
-    d.P_pad = L.pl.P_pad;
     d.k = n_groups;
-    d.pad = 0;
+    d.kind = kind;
+    d.R = R;
+    if (kind == 0) {
+        launch_stage_labels_om(L.head.allg, nullptr, n, R, L.pl.n_pad, L.pl.P_pad, n_groups, L.lab,
+                               L.bad, tls.flags, s);
+        d.lab = L.lab;
+        d.partial = L.partial;
+        d.nt = L.pl.n_t;
+        d.n_tiles = L.pl.n_tiles;
+        d.tiles_per_chunk = L.pl.tiles_per_chunk;
+        d.P_pad = L.pl.P_pad;
+    } else {
+        launch_stage_labels_pm(L.head.allg, n, R, L.mp.n_pad, L.mp.P_pad, n_groups, L.lab, L.bad,
+                               tls.flags, s);
+        launch_mfma_prepass(mat, n, 2, L.tiles, s);
+        launch_item_table(L.mp, L.tab, s);
+        d.tiles = L.tiles;
+        d.lab_pm = L.lab;
+        d.tab = L.tab;
+        d.z = L.z;
+        d.comp_units = L.mp.panels * (L.mp.panels + 1);
+        d.kb_total = L.mp.kb_total;
+        d.n_pad_m = L.mp.n_pad;
+    }
+    if ((rc = check_launch("job staging"))) return rc;
     HIP_TRY(hipMemcpyAsync(sv->jobs_dev + slot, &d, sizeof(JobDesc), hipMemcpyHostToDevice, s));
 
     Job &J = sv->jobs[slot];
     J.live = true;
+    J.kind = kind;
     J.mat = mat;
     J.n = n;
     J.n_perms = n_perms;
     J.k = n_groups;
     J.head = L.head;
     J.pl = L.pl;
+    J.mp = L.mp;
     J.lab = L.lab;
     J.partial = L.partial;
+    J.z = L.z;
+    J.tmp = L.tmp;
     J.bad = L.bad;
-    J.units = L.pl.chunks * L.pl.pgroups;
+    if (kind == 0) {
+        J.units = L.pl.chunks * L.pl.pgroups;
+        J.split = L.pl.pgroups;
+    } else {
+        J.units = L.mp.items * L.mp.nblocks;
+        J.split = L.mp.nblocks;
+    }
     *job = slot;
     *n_units = J.units;
     return PSTAT_OK;
@@ -245,8 +307,10 @@ int pstat_serve_round(int64_t server, const int64_t *units, int64_t count) {
         HIP_TRY(hipEventSynchronize(sv->done[b]));
         sv->in_flight[b] = false;
     }
-    // Host pairs (job, unit) -> (job, chunk, permutation group); units of a
-    // job are numbered chunk-major so neighbouring units share tiles.
+    // Host pairs (job, unit) -> (job, a, b) in the list of the job's kind:
+    // plain (tile chunk, permutation group), MFMA (work item, column block);
+    // a job's units are numbered a-major so neighbouring units share data.
+    int32_t cnt[2] = {0, 0};
     for (int64_t i = 0; i < count; i++) {
         const int64_t j = units[2 * i], u = units[2 * i + 1];
         if (j < 0 || j >= sv->max_jobs || !sv->jobs[j].live)
@@ -255,26 +319,33 @@ int pstat_serve_round(int64_t server, const int64_t *units, int64_t count) {
         const Job &J = sv->jobs[j];
         if (u < 0 || u >= J.units)
             return fail(PSTAT_EINVAL, "unit %lld of job %lld out of range", (long long)u, (long long)j);
-        sv->units_host[b][i] = UnitDesc{(int32_t)j, (int32_t)(u / J.pl.pgroups),
-                                        (int32_t)(u % J.pl.pgroups)};
+        sv->units_host[b][J.kind][cnt[J.kind]++] =
+            UnitDesc{(int32_t)j, (int32_t)(u / J.split), (int32_t)(u % J.split)};
     }
-    sv->count_host[b][0] = (int32_t)count;
+    sv->count_host[b][0] = cnt[0];
+    sv->count_host[b][1] = cnt[1];
     if (!sv->exec[b]) {
         hipStream_t s = tls.stream;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-        hipError_t e1 = hipMemcpyAsync(sv->units_dev[b], sv->units_host[b],
-                                       sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
-        hipError_t e2 = hipMemcpyAsync(sv->count_dev[b], sv->count_host[b], sizeof(int32_t),
-                                       hipMemcpyHostToDevice, s);
-        launch_plain_worklist(sv->jobs_dev, sv->units_dev[b], sv->count_dev[b], sv->max_units, s);
-        hipError_t e3 = hipGetLastError();
+        hipError_t e[6];
+        e[0] = hipMemcpyAsync(sv->units_dev[b][0], sv->units_host[b][0],
+                              sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
+        e[1] = hipMemcpyAsync(sv->units_dev[b][1], sv->units_host[b][1],
+                              sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
+        e[2] = hipMemcpyAsync(sv->count_dev[b], sv->count_host[b], 2 * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s);
+        launch_plain_worklist(sv->jobs_dev, sv->units_dev[b][0], sv->count_dev[b], sv->max_units, s);
+        e[3] = hipGetLastError();
+        launch_mfma_worklist(sv->jobs_dev, sv->units_dev[b][1], sv->count_dev[b] + 1,
+                             sv->max_units, s);
+        e[4] = hipGetLastError();
         hipGraph_t g = nullptr;
-        hipError_t e4 = hipStreamEndCapture(s, &g);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : e4,
-                            "capturing the serving round");
-        }
+        e[5] = hipStreamEndCapture(s, &g);
+        for (int q = 0; q < 6; q++)
+            if (e[q] != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e[q], "capturing the serving round");
+            }
         sv->graph[b] = g;
         HIP_TRY(hipGraphInstantiate(&sv->exec[b], g, nullptr, nullptr, 0));
     }
@@ -298,13 +369,17 @@ int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all
     const Job &J = sv->jobs[job];
     const int64_t R = J.n_perms + 1;
     hipStream_t s = tls.stream;
-    launch_reduce_plain(J.partial, J.pl.chunks, J.pl.P_pad, R, J.bad, J.head.sw, s);
+    if (J.kind == 0)
+        launch_reduce_plain(J.partial, J.pl.chunks, J.pl.P_pad, R, J.bad, J.head.sw, s);
+    else
+        launch_reduce_mfma(J.z, J.mp.items, R, J.k, J.head.w, J.bad, J.tmp, J.head.sw, s);
     if ((rc = check_launch("job reduce"))) return rc;
     const size_t region = plain_bytes_bound(J.n, R, PSTAT_PATH_PLAIN_F64);
     char *ws;
     if ((rc = acquire_workspace(region, &ws))) return rc;
     int64_t rechecked = 0;
-    if ((rc = finish_test(J.head, J.mat, J.n, J.k, J.n_perms, PSTAT_PATH_PLAIN_F32, ws, region,
+    if ((rc = finish_test(J.head, J.mat, J.n, J.k, J.n_perms,
+                          J.kind == 0 ? PSTAT_PATH_PLAIN_F32 : PSTAT_PATH_MFMA_SPLIT_BF16, ws, region,
                           &rechecked)))
         return rc;
     if (sW_all)

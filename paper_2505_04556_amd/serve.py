@@ -75,13 +75,22 @@ class Executor:
 
 
 class GpuExecutor(Executor):
-    """Executor on the pstat C ABI; all work on one created stream."""
+    """Executor on the pstat C ABI; all work on one created stream.
 
-    def __init__(self, max_jobs: int = 64, max_units: int = 8192, device=None):
+    ``path`` picks each job's form: "plain_f32", "mfma_split_bf16" or "auto"
+    (the library's choice by n and k).  Unit costs are in plain-kernel
+    pair-permutations, so one round budget covers both forms: an MFMA unit's
+    pair-permutations count ``mfma_speedup`` times less."""
+
+    mfma_speedup = 6.0     # split-BF16 MFMA vs plain FP32 throughput, n >= 5,000
+
+    def __init__(self, max_jobs: int = 64, max_units: int = 8192, device=None,
+                 path: str = "auto"):
         import torch
 
         import paper_2505_04556_amd as ps
         self.ps, self.torch = ps, torch
+        self.path = path
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.Stream(self.device)     # default priority
         self.max_units = max_units
@@ -91,21 +100,27 @@ class GpuExecutor(Executor):
 
     def footprint(self, req: Request) -> int:
         ps = self.ps
-        return 4 * req.n * req.n + ps.pstat_job_bytes(req.n, req.n_perms, req.k) + 4 * req.n
+        return (4 * req.n * req.n + ps.pstat_job_bytes(req.n, req.n_perms, req.k, self.path)
+                + 4 * req.n)
+
+    def form(self, req: Request) -> str:
+        return self.ps.resolve_path(self.path, req.n, req.k)
 
     def create(self, req: Request):
         torch, ps = self.torch, self.ps
         with torch.cuda.stream(self.stream):
             mat = req.make_matrix(self.device)
             g = torch.from_numpy(np.ascontiguousarray(req.grouping, dtype=np.int32)).to(self.device)
-            scratch = torch.empty(ps.pstat_job_bytes(req.n, req.n_perms, req.k), dtype=torch.uint8,
-                                  device=self.device)
+            scratch = torch.empty(ps.pstat_job_bytes(req.n, req.n_perms, req.k, self.path),
+                                  dtype=torch.uint8, device=self.device)
             job, units = ps.pstat_job_create(self.server, mat, g, req.k, req.n_perms, req.seed,
-                                             scratch)
-        # work of one unit in pair-permutations (a tile chunk for 256
-        # permutation lanes); used only to size rounds
+                                             scratch, self.path)
+        # work of one unit in plain-kernel pair-permutations; used only to
+        # size rounds
         pairs = req.n * (req.n - 1) / 2
         unit_cost = pairs * (req.n_perms + 1) / max(1, units)
+        if self.form(req) == "mfma_split_bf16":
+            unit_cost /= self.mfma_speedup
         self.live[job] = (mat, g, scratch, req.n_perms + 1)
         return job, units, unit_cost
 

@@ -1,6 +1,8 @@
 """Serving on the GPU: continuous batching of several permutation tests whose
 work shares launches; every result must be bit-identical alone and in the mix,
-equal to the whole-test call on the same form, and match the FP64 oracle."""
+equal to the whole-test call on the same form, and match the FP64 oracle.  Jobs
+run on the plain FP32 form, the split-BF16 MFMA form, or a mix of both (auto:
+the small test takes the plain form, so rounds launch both work-list kernels)."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,8 @@ def requests(device_gen=True):
     from paper_2505_04556_amd.serve import Request
     import synth.device as sd
     specs = [(600, [100, 200, 300], 199), (1000, [500, 500], 511), (1500, [300, 500, 700], 299),
-             (800, [100, 150, 250, 300], 399), (1200, [600, 600], 255), (700, [350, 350], 1023)]
+             (800, [100, 150, 250, 300], 399), (1200, [600, 600], 255), (700, [350, 350], 1023),
+             (400, [150, 250], 255)]
     reqs = []
     for i, (n, sizes, P) in enumerate(specs):
         base = synth.base_labels(sizes)
@@ -30,9 +33,9 @@ def ps(dev):
     return load_pstat()
 
 
-def serve(reqs, budget=8 << 30, round_work=1e8):
+def serve(reqs, budget=8 << 30, round_work=1e8, path="plain_f32"):
     from paper_2505_04556_amd.serve import GpuExecutor, Server
-    ex = GpuExecutor(max_jobs=16, max_units=4096)
+    ex = GpuExecutor(max_jobs=16, max_units=4096, path=path)
     try:
         srv = Server(ex, hbm_budget=budget, keep_sW=True, round_work=round_work, max_units=4096)
         return srv.run(reqs), srv
@@ -40,22 +43,26 @@ def serve(reqs, budget=8 << 30, round_work=1e8):
         ex.close()
 
 
-def test_mix_equals_alone_and_oracle(ps):
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "auto"])
+def test_mix_equals_alone_and_oracle(ps, path):
     import torch
     reqs = requests()
-    mixed, srv = serve(reqs)
+    # small rounds, so every job spans several (MFMA units are larger)
+    rw = 1e8 if path == "plain_f32" else 4e6
+    mixed, srv = serve(reqs, path=path, round_work=rw)
     assert mixed["stats"]["completed"] == len(reqs)
-    # rounds carried work of several jobs (small rounds: every job spans several)
+    # rounds carried work of several jobs
     assert max(jobs for _, _, jobs in srv.log) >= 2
     assert srv.log and len(srv.log) > len(reqs)
     for r in reqs:
-        alone, _ = serve([r])
+        alone, _ = serve([r], path=path, round_work=rw)
         a = alone["outcomes"][r.id]
         m = mixed["outcomes"][r.id]
         assert a.result == m.result, r.id
         assert np.array_equal(a.sW_all, m.sW_all), r.id
-        # same numbers as the whole-test entry point on the plain FP32 form
-        ps.pstat_set_path("plain_f32")
+        # same numbers as the whole-test entry point on the same form
+        form = ps.resolve_path(path, r.n, r.k)
+        ps.pstat_set_path(form)
         D = r.make_matrix(torch.device("cuda"))
         sw = torch.empty(r.n_perms + 1, dtype=torch.float64, device="cuda")
         res, _ = ps.pstat_permanova(D, torch.from_numpy(r.grouping).cuda(), r.k, r.n_perms,
@@ -67,6 +74,7 @@ def test_mix_equals_alone_and_oracle(ps):
         assert max_rel(m.sW_all[1:], ref["sW_perm"]) <= 1e-5
         assert abs(m.result[0] - ref["F_obs"]) <= 1e-5 * abs(ref["F_obs"])
         assert m.result[1] == ref["p"]
+    ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
 
 
 def test_admission_under_a_small_budget(ps):

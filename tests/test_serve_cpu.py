@@ -152,3 +152,15 @@ def test_nearest_rank_quantiles():
     assert nearest_rank(v, 0.99) == 64      # ceil(0.99 * 64) = 64: p99 is the maximum
     assert nearest_rank([5.0], 0.99) == 5.0
     assert math.isnan(nearest_rank([], 0.5))
+
+
+def test_autotune_keys_and_cache(tmp_path):
+    from paper_2505_04556_amd import autotune
+    assert autotune.bucket(1) == 1 and autotune.bucket(1000) == 1024 and autotune.bucket(1024) == 1024
+    k1 = autotune.shape_key(10_000, 5, 9_999)
+    assert k1 == autotune.shape_key(9_000, 5, 9_000)       # same buckets
+    assert k1 != autotune.shape_key(10_000, 6, 9_999)
+    f = str(tmp_path / "c.json")
+    autotune.save_cache({"a": {"x": 1}}, f)
+    assert autotune.load_cache(f) == {"a": {"x": 1}}
+    assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
