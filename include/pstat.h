@@ -74,7 +74,9 @@ int pstat_init(int device);
 int pstat_set_stream(void *hip_stream);
 
 /* Form used by pstat_sW / pstat_sW_k / pstat_permanova on this thread.
- * PSTAT_PATH_AUTO (default) = the tuned choice for the problem shape. */
+ * PSTAT_PATH_AUTO (default) = the tuned choice for the problem shape.  The
+ * MFMA forms need at least two groups: with a single group the plain FP32
+ * form runs instead. */
 int pstat_set_path(int path);
 
 /* The form PSTAT_PATH_AUTO stands for at n objects and n_groups groups (other
@@ -85,7 +87,8 @@ int pstat_resolve_path(int path, int64_t n, int32_t n_groups);
 /* Tuning of one path for this thread: `tile` and `batch` override the tuned
  * values (0 = keep the tuned value).  Plain paths: tile = square tile edge
  * (32 or 64), batch = permutation lanes per work-group (64, 128 or 256).  MFMA
- * paths: tile = K-chunk length in columns (multiple of 64, 0 = tuned), batch =
+ * paths: tile = K-chunk length in columns (multiple of 64, rounded up to a
+ * multiple of 128; 0 = tuned), batch =
  * N columns per work-group (256 or 512).  Invalid values give PSTAT_EINVAL. */
 int pstat_set_tuning(int path, int tile, int batch);
 

@@ -35,6 +35,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kPanel = 128;      // rows per panel
 constexpr int kKBlock = 64;      // columns per K block
 constexpr int kUnitU4 = 1024;    // uint4 per (panel, K block) unit per component (16 KB)
+// s_waitcnt operand that waits for LDS/scalar loads only: lgkmcnt(0), with the
+// vector-memory (vmcnt 63) and export (expcnt 7) fields left at their maxima
+constexpr int kLgkmOnly = 0xC07F;
 
 // bits of 1.0 in the MFMA input type
 template <int DT>
@@ -158,36 +161,60 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 
 // DT: 0 bf16, 1 f16, 2 split bf16 (hi and lo MFMAs into one accumulator).
 // NF: 32-column fragments per wave; a work-group of 4 waves covers 128 rows x
-// (4 * NF * 32) columns.  The K blocks of A (the pre-squared tiles) are staged
-// once per work-group in double-buffered LDS and read by all four waves; each
-// wave builds its own one-hot B fragments from u16 labels, one K step ahead.
-template <int DT, int NF>
-__device__ __attribute__((always_inline)) inline void mfma_unit(const uint4 *__restrict__ tiles, int64_t comp_units,
-                                 int64_t kb_total, const int32_t *__restrict__ tab, int64_t item,
-                                 int64_t nb, const uint16_t *__restrict__ lab, int64_t n_pad,
-                                 int32_t k, int64_t P, float *__restrict__ z) {
+// (4 * NF * 32) columns.
+//
+// Pipeline.  Each K block is copied global -> LDS by the direct-to-LDS load
+// (no registers): the block of A (the pre-squared tiles) and the 64 labels of
+// every permutation the work-group's columns belong to.  The copy of block
+// kb + 1 is issued before block kb is computed and waited for at the barrier
+// that ends block kb, so it has a whole block of MFMA work to land.  All
+// operands of the MFMAs then come from LDS, none from global memory: the
+// vector-memory counter retires in issue order, so waiting for any global load
+// issued after the copy would also wait for the copy.  Two LDS buffers of each
+// kind are separate variables and the loop is unrolled by two (items have an
+// even number of K blocks), so every access names its buffer statically and
+// the compiler can see that reads of one buffer do not depend on the copy into
+// the other.
+template <int DT, int NF, int LQ>
+__device__ __attribute__((always_inline)) inline void mfma_unit(
+    const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
+    const int32_t *__restrict__ tab, int64_t item, int64_t nb, const uint16_t *__restrict__ lab,
+    int64_t n_pad, int32_t k, int64_t P, float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
     constexpr int NC = DT == 2 ? 2 : 1;     // A components (hi, lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
     constexpr int COLS = 4 * NF * 32;       // columns per work-group
-    __shared__ uint4 sA[2][UNIT];
+    // Labels of one K block: per permutation 8 chunks of 8 u16 (16 bytes) and
+    // one pad chunk (a stride of 9 chunks spreads neighbouring permutations
+    // over the LDS banks); LQ * 256 slots hold the (COLS - 1) / k + 2
+    // permutations a work-group's columns can touch (the launch picks LQ).
+    constexpr int kLStride = 9;
+    constexpr int LSLOTS = LQ * 256;
+    __shared__ uint4 sA0[UNIT];
+    __shared__ uint4 sA1[UNIT];
+    __shared__ uint4 sL0[LSLOTS];
+    __shared__ uint4 sL1[LSLOTS];
     const int64_t I = tab[3 * item], kb0 = tab[3 * item + 1], kb1 = tab[3 * item + 2];
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
     const int half = lane / 32, col = lane % 32;
     const int64_t NK = (int64_t)k * P;
+    // permutations of this work-group's columns (p_hi < the padded count)
+    const int64_t p_lo = nb * COLS / k;
+    const int64_t p_hi = (nb * COLS + COLS - 1) / k;
 
     int64_t cidx[NF], pcol[NF];
     int32_t gcol[NF];
     uint32_t gg[NF];
-    const uint16_t *labrow[NF];
+    int lslot[NF];
 #pragma unroll
     for (int nf = 0; nf < NF; nf++) {
         cidx[nf] = nb * COLS + wave * (NF * 32) + nf * 32 + col;
         pcol[nf] = cidx[nf] / k;
         gcol[nf] = (int32_t)(cidx[nf] % k);
         gg[nf] = (uint32_t)gcol[nf] | ((uint32_t)gcol[nf] << 16);
-        labrow[nf] = lab + pcol[nf] * n_pad + 32 * half;
+        // K step s of a block uses rows 8s + 32*half + 0..7: chunk s + 4*half
+        lslot[nf] = (int)(pcol[nf] - p_lo) * kLStride + 4 * half;
     }
 
     f32x16 acc[4][NF];
@@ -199,60 +226,117 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(const uint4 *__r
             for (int v = 0; v < 16; v++) acc[rb][nf][v] = 0.0f;
 
     const int64_t panel_off = I * kb_total - I * (I - 1);
-    // Direct global -> LDS copy of one staged K block: lane l of wave w moves
-    // uint4 number q*256 + 64w + l of the block (both sides in fragment order).
-    auto stage = [&](int64_t kb, int buf) {
+    // Copy of K block kb: lane l of wave w moves uint4 number q*256 + 64w + l
+    // (A: both sides in fragment order; labels: slot j = 9 * perm + chunk,
+    // the pad chunk repeating chunk 0 and slots past the last permutation
+    // repeating it, so every source address is inside the label array).
+    auto stage = [&](int64_t kb, uint4 *dA, uint4 *dL) {
 #pragma unroll
         for (int q = 0; q < UNIT / 256; q++) {
             const uint4 *src = tiles + ((int64_t)(q / 4) * comp_units + panel_off + (kb - 2 * I)) *
                                            kUnitU4 + (q % 4) * 256 + tid;
             __builtin_amdgcn_global_load_lds(
                 (__attribute__((address_space(1))) void *)src,
-                (__attribute__((address_space(3))) void *)&sA[buf][q * 256 + wave * 64], 16, 0, 0);
+                (__attribute__((address_space(3))) void *)&dA[q * 256 + wave * 64], 16, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < LQ; q++) {
+            const int j = q * 256 + tid;
+            const int pr = j / kLStride;
+            int ch = j - pr * kLStride;
+            if (ch == kLStride - 1) ch = 0;
+            int64_t p = p_lo + pr;
+            if (p > p_hi) p = p_hi;
+            const uint16_t *src = lab + p * n_pad + kb * kKBlock + ch * 8;
+            __builtin_amdgcn_global_load_lds(
+                (__attribute__((address_space(1))) void *)src,
+                (__attribute__((address_space(3))) void *)&dL[q * 256 + wave * 64], 16, 0, 0);
         }
     };
-    stage(kb0, 0);
+    // Software pipeline over K steps: the A fragments and labels of step t+1
+    // are read from LDS before the MFMAs of step t are issued, and B(t+1) is
+    // built from those labels while the second half of step t's MFMAs run.
+    // Scheduling barriers pin this order (left to itself the compiler reads
+    // each A fragment just before its MFMAs, exposing the LDS latency).
+    uint4 Ac[4][NC], An[4][NC];
+    uint4 Ln[NF], B[NF];
+    auto load_step = [&](const uint4 *cA, const uint4 *cL, int s) {
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int c = 0; c < NC; c++) An[rb][c] = cA[c * kUnitU4 + (rb * 4 + s) * 64 + lane];
+#pragma unroll
+        for (int nf = 0; nf < NF; nf++) Ln[nf] = cL[lslot[nf] + s];
+    };
+    // MFMAs of the current step, then B and A of the next one.
+    auto step = [&]() {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int nf = 0; nf < NF; nf++)
+                    acc[rb][nf] = mma<BT>(Ac[rb][c], B[nf], acc[rb][nf]);
+#pragma unroll
+        for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(Ln[nf], gg[nf]);
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int c = 0; c < NC; c++) Ac[rb][c] = An[rb][c];
+        // first half of the MFMAs alone, then one MFMA per three VALU
+#pragma unroll
+        for (int i = 0; i < 2 * NF * NC; i++) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+        for (int i = 0; i < 2 * NF * NC; i++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // Block kb from (cA, cL); the copy of block kb + 1 into (nA, nL) was
+    // issued one block earlier.  The barrier sits before the last step: by
+    // then every read of (cA, cL) has been issued and waited for, so the copy
+    // of block kb + 2 may reuse them, and the next block's first operands are
+    // read while the last step's MFMAs run.  Past the item's last block the
+    // copy repeats that block and the reads of the next one are not used:
+    // every address stays in range and the code stays branch-free.
+    auto block = [&](int64_t kb, uint4 *cA, uint4 *cL, const uint4 *nA, const uint4 *nL) {
+        load_step(cA, cL, 1);
+        step();
+        load_step(cA, cL, 2);
+        step();
+        load_step(cA, cL, 3);
+        step();
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed
+        __syncthreads();                 // ... and every wave's; reads of cA done
+        stage(kb + 2 < kb1 ? kb + 2 : kb1 - 1, cA, cL);
+        load_step(nA, nL, 0);
+        step();
+        // The next block's A fragments were read a whole step ago; saying so
+        // here keeps the wait for them out of the loop's first MFMAs (the
+        // compiler cannot track LDS reads across the loop's back edge).
+        __builtin_amdgcn_s_waitcnt(kLgkmOnly);
+    };
+
+    stage(kb0, sA0, sL0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-
-    uint4 L[NF];
+    stage(kb0 + 1, sA1, sL1);
+    load_step(sA0, sL0, 0);
 #pragma unroll
-    for (int nf = 0; nf < NF; nf++) L[nf] = *(const uint4 *)(labrow[nf] + kb0 * kKBlock);
-
-    for (int64_t kb = kb0; kb < kb1; kb++) {
-        const int buf = (int)((kb - kb0) & 1);
-        const bool more = kb + 1 < kb1;
-        // The other buffer was last read before the previous barrier.
-        if (more) stage(kb + 1, buf ^ 1);
+    for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(Ln[nf], gg[nf]);
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-            uint4 B[NF];
+    for (int rb = 0; rb < 4; rb++)
 #pragma unroll
-            for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(L[nf], gg[nf]);
-            // labels of the next K step (or the next K block's first step)
-            if (s < 3) {
-#pragma unroll
-                for (int nf = 0; nf < NF; nf++)
-                    L[nf] = *(const uint4 *)(labrow[nf] + kb * kKBlock + 8 * (s + 1));
-            } else if (more) {
-#pragma unroll
-                for (int nf = 0; nf < NF; nf++)
-                    L[nf] = *(const uint4 *)(labrow[nf] + (kb + 1) * kKBlock);
-            }
-#pragma unroll
-            for (int rb = 0; rb < 4; rb++) {
-#pragma unroll
-                for (int c = 0; c < NC; c++) {
-                    const uint4 A = sA[buf][c * kUnitU4 + (rb * 4 + s) * 64 + lane];
-#pragma unroll
-                    for (int nf = 0; nf < NF; nf++) acc[rb][nf] = mma<BT>(A, B[nf], acc[rb][nf]);
-                }
-            }
-        }
-        // the next block's copy has landed in LDS for every wave
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        for (int c = 0; c < NC; c++) Ac[rb][c] = An[rb][c];
+    __builtin_amdgcn_s_waitcnt(kLgkmOnly);
+    for (int64_t kb = kb0; kb < kb1; kb += 2) {
+        block(kb, sA0, sL0, sA1, sL1);
+        block(kb + 1, sA1, sL1, sA0, sL0);
     }
+    // the last copy (a repeat) must land before the work-group ends
+    __builtin_amdgcn_s_waitcnt(0);
 
     // Epilogue: keep the rows whose label equals the column's group.
     const int64_t i0 = I * kPanel;
@@ -277,7 +361,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(const uint4 *__r
     }
 }
 
-template <int DT, int NF>
+template <int DT, int NF, int LQ>
 __global__ __launch_bounds__(256) void k_mfma(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
@@ -287,12 +371,23 @@ __global__ __launch_bounds__(256) void k_mfma(
     const int64_t bid = blockIdx.x;
     const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
     if (logical >= grid_real) return;
-    mfma_unit<DT, NF>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
-                      lab, n_pad, k, P, z);
+    mfma_unit<DT, NF, LQ>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
+                          lab, n_pad, k, P, z);
+}
+
+// Label-copy rounds for the permutations that COLS columns of k groups can
+// touch ((COLS - 1) / k + 2, 9 slots each, 256 per round), rounded up to the
+// instantiated counts.
+constexpr int kLqBins[4] = {2, 4, 7, 10};
+int lq_bin(int cols, int32_t k) {
+    const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 9, 256);
+    for (int b : kLqBins)
+        if (need <= b) return b;
+    return -1;
 }
 
 // Work-list form (serving): block b runs unit units[b] = (job, item, column
-// block) of a split-BF16 job in the job table.
+// block) of a split-BF16 job in the job table (labels staged for any k >= 2).
 __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict__ jobs,
                                                       const UnitDesc *__restrict__ units,
                                                       const int32_t *__restrict__ count) {
@@ -302,8 +397,8 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
     if (logical >= *count) return;
     const UnitDesc u = units[logical];
     const JobDesc &j = jobs[u.job];
-    mfma_unit<2, 4>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk, u.pgroup,
-                    j.lab_pm, j.n_pad_m, j.k, j.R, j.z);
+    mfma_unit<2, 4, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
+                        u.pgroup, j.lab_pm, j.n_pad_m, j.k, j.R, j.z);
 }
 
 } // namespace
@@ -323,7 +418,10 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     pl.panels = pl.n_pad / kPanel;
     pl.kb_total = pl.n_pad / kKBlock;
     int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock : 16;
-    if (kc < 1) kc = 1;
+    // the kernel takes K blocks in pairs: every item's length is even
+    // (each panel's range [2I, kb_total) has even length)
+    if (kc < 2) kc = 2;
+    kc += kc & 1;
     pl.kchunk = kc;
     int64_t items = 0;
     for (int64_t I = 0; I < pl.panels; I++) items += ceil_div(pl.kb_total - 2 * I, kc);
@@ -350,30 +448,42 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     else hipLaunchKernelGGL(k_prepass<2>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, t);
 }
 
-template <int DT, int NF>
+template <int DT, int NF, int LQ>
 void launch_mfma_t(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
                    int64_t grid_real, int64_t gpad, const uint16_t *lab, int32_t k, int64_t P,
                    float *z, hipStream_t s) {
-    hipLaunchKernelGGL((k_mfma<DT, NF>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
+    hipLaunchKernelGGL((k_mfma<DT, NF, LQ>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
                        pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad, k, P, z);
+}
+
+template <int DT, int NF>
+int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
+                   int64_t grid_real, int64_t gpad, const uint16_t *lab, int32_t k, int64_t P,
+                   float *z, hipStream_t s) {
+    switch (lq_bin(4 * NF * 32, k)) {
+    case 2: launch_mfma_t<DT, NF, 2>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+    case 4: launch_mfma_t<DT, NF, 4>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+    case 7: launch_mfma_t<DT, NF, 7>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+    case 10: launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+    }
+    return -1;
 }
 
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
                 int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s) {
     (void)n;
     if (pl.ncols != 256 && pl.ncols != 512) return -1;
+    if (k < 2 || (pl.kchunk & 1)) return -1;
     hipLaunchKernelGGL(k_item_table, dim3(1), dim3(64), 0, s, pl.panels, pl.kb_total, pl.kchunk, tab);
     const int64_t grid_real = pl.items * pl.nblocks;
     const int64_t gpad = round_up(grid_real, 8);
     const int64_t comp_units = pl.panels * (pl.panels + 1);
     const uint4 *t = (const uint4 *)tiles;
-#define PSTAT_MFMA_CASE(DT_)                                                                   \
-    if (pl.dtype == DT_) {                                                                     \
-        if (pl.ncols == 512)                                                                   \
-            launch_mfma_t<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
-        else                                                                                   \
-            launch_mfma_t<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
-        return 0;                                                                              \
+#define PSTAT_MFMA_CASE(DT_)                                                                      \
+    if (pl.dtype == DT_) {                                                                        \
+        if (pl.ncols == 512)                                                                      \
+            return launch_mfma_lq<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
+        return launch_mfma_lq<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s);     \
     }
     PSTAT_MFMA_CASE(0)
     PSTAT_MFMA_CASE(1)

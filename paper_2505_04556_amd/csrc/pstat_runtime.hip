@@ -127,8 +127,12 @@ int mfma_dtype(int path) {
 // three VALU operations for the plain kernel at 1/64 of the matrix-core rate,
 // so it wins while k stays small; tiny matrices stay on the plain kernel.
 int resolve_path(int path, int64_t n, int32_t k) {
-    if (path != PSTAT_PATH_AUTO) return path;
-    return (n >= 512 && k <= 16) ? PSTAT_PATH_MFMA_SPLIT_BF16 : PSTAT_PATH_PLAIN_F32;
+    if (path == PSTAT_PATH_AUTO)
+        return (n >= 512 && k >= 2 && k <= 16) ? PSTAT_PATH_MFMA_SPLIT_BF16 : PSTAT_PATH_PLAIN_F32;
+    // The MFMA kernels stage the labels of at most half a work-group's
+    // columns' worth of permutations (k >= 2); a single group runs plain.
+    if (is_mfma(path) && k < 2) return PSTAT_PATH_PLAIN_F32;
+    return path;
 }
 
 void plain_params(int path, int64_t P, int *tile, int *lanes) {
