@@ -78,6 +78,11 @@ struct JobDesc {              // one staged problem, device-resident
 struct UnitDesc {             // one work-group's share of one job: plain
     int32_t job, chunk, pgroup;   // (tile chunk, permutation group); MFMA
 };                                // (work item, column block)
+// FP64 s_W of m groupings (rows[q] of g, [*][n] int32, labels in [0, k)) in
+// one pass over D: out[q] for q < m.  partial: few_partial_bytes(n, m) bytes.
+size_t few_partial_bytes(int64_t n, int64_t m);
+void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
+                   int32_t k, const double *w, double *partial, double *out, hipStream_t s);
 void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                            int64_t max_units, hipStream_t s);
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,

@@ -198,23 +198,22 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
     const int half = lane / 32, col = lane % 32;
-    const int64_t NK = (int64_t)k * P;
     // permutations of this work-group's columns (p_hi < the padded count)
     const int64_t p_lo = nb * COLS / k;
     const int64_t p_hi = (nb * COLS + COLS - 1) / k;
 
-    int64_t cidx[NF], pcol[NF];
-    int32_t gcol[NF];
+    // Per column fragment: its group (both 16-bit halves) and the LDS label
+    // slot of its permutation (everything else is derived from these two).
     uint32_t gg[NF];
     int lslot[NF];
 #pragma unroll
     for (int nf = 0; nf < NF; nf++) {
-        cidx[nf] = nb * COLS + wave * (NF * 32) + nf * 32 + col;
-        pcol[nf] = cidx[nf] / k;
-        gcol[nf] = (int32_t)(cidx[nf] % k);
-        gg[nf] = (uint32_t)gcol[nf] | ((uint32_t)gcol[nf] << 16);
+        const int64_t c = nb * COLS + wave * (NF * 32) + nf * 32 + col;
+        const int64_t p = c / k;
+        const uint32_t g = (uint32_t)(c - p * k);
+        gg[nf] = g | (g << 16);
         // K step s of a block uses rows 8s + 32*half + 0..7: chunk s + 4*half
-        lslot[nf] = (int)(pcol[nf] - p_lo) * kLStride + 4 * half;
+        lslot[nf] = (int)(p - p_lo) * kLStride + 4 * half;
     }
 
     f32x16 acc[4][NF];
@@ -230,15 +229,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // (A: both sides in fragment order; labels: slot j = 9 * perm + chunk,
     // the pad chunk repeating chunk 0 and slots past the last permutation
     // repeating it, so every source address is inside the label array).
-    auto stage = [&](int64_t kb, uint4 *dA, uint4 *dL) {
-#pragma unroll
-        for (int q = 0; q < UNIT / 256; q++) {
-            const uint4 *src = tiles + ((int64_t)(q / 4) * comp_units + panel_off + (kb - 2 * I)) *
-                                           kUnitU4 + (q % 4) * 256 + tid;
-            __builtin_amdgcn_global_load_lds(
-                (__attribute__((address_space(1))) void *)src,
-                (__attribute__((address_space(3))) void *)&dA[q * 256 + wave * 64], 16, 0, 0);
-        }
+    auto stage_labels = [&](int64_t kb, uint4 *dL) {
 #pragma unroll
         for (int q = 0; q < LQ; q++) {
             const int j = q * 256 + tid;
@@ -252,6 +243,17 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                 (__attribute__((address_space(1))) void *)src,
                 (__attribute__((address_space(3))) void *)&dL[q * 256 + wave * 64], 16, 0, 0);
         }
+    };
+    auto stage = [&](int64_t kb, uint4 *dA, uint4 *dL) {
+#pragma unroll
+        for (int q = 0; q < UNIT / 256; q++) {
+            const uint4 *src = tiles + ((int64_t)(q / 4) * comp_units + panel_off + (kb - 2 * I)) *
+                                           kUnitU4 + (q % 4) * 256 + tid;
+            __builtin_amdgcn_global_load_lds(
+                (__attribute__((address_space(1))) void *)src,
+                (__attribute__((address_space(3))) void *)&dA[q * 256 + wave * 64], 16, 0, 0);
+        }
+        stage_labels(kb, dL);
     };
     // Software pipeline over K steps: the A fragments and labels of step t+1
     // are read from LDS before the MFMAs of step t are issued, and B(t+1) is
@@ -338,26 +340,47 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // the last copy (a repeat) must land before the work-group ends
     __builtin_amdgcn_s_waitcnt(0);
 
-    // Epilogue: keep the rows whose label equals the column's group.
-    const int64_t i0 = I * kPanel;
+    // Epilogue: keep the rows whose label equals the column's group.  The
+    // panel's 128 rows are K blocks 2I and 2I + 1, so their labels are copied
+    // into the two label buffers in the same layout as in the loop.
+    __syncthreads();                 // every wave is done with the buffers
+    stage_labels(2 * I, sL0);
+    stage_labels(2 * I + 1, sL1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
 #pragma unroll
     for (int nf = 0; nf < NF; nf++) {
-        const uint16_t *lr = lab + pcol[nf] * n_pad + i0;
+        // Derived again from the loop's two registers (an empty asm hides
+        // their origin), so nothing else stays live across the K loop.
+        int sl = lslot[nf];
+        uint32_t gv = gg[nf];
+        asm volatile("" : "+v"(sl), "+v"(gv));
+        const int slot0 = sl - 4 * half;   // chunk 0 of this permutation
+        const uint32_t g = gv & 0xFFFFu;
+        uint2 l4[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++) {
+            const uint2 *L2 = reinterpret_cast<const uint2 *>(rb < 2 ? sL0 : sL1);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+                // rows rb*32 + 8a + 4*half + 0..3 of the panel: chunk
+                // (rb % 2) * 4 + a of its K block, bytes 8*half .. 8*half + 7
+                l4[rb][a] = L2[(slot0 + (rb % 2) * 4 + a) * 2 + half];
+        }
         float zs = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                // rows rb*32 + 8a + 4*half + 0..3 of the panel
-                const uint2 l4 = *(const uint2 *)(lr + rb * 32 + 8 * a + 4 * half);
-                const uint32_t lab4[4] = {l4.x & 0xFFFFu, l4.x >> 16, l4.y & 0xFFFFu, l4.y >> 16};
+                const uint32_t lab4[4] = {l4[rb][a].x & 0xFFFFu, l4[rb][a].x >> 16,
+                                          l4[rb][a].y & 0xFFFFu, l4[rb][a].y >> 16};
 #pragma unroll
-                for (int b = 0; b < 4; b++)
-                    zs += (lab4[b] == (uint32_t)gcol[nf]) ? acc[rb][nf][4 * a + b] : 0.0f;
+                for (int b = 0; b < 4; b++) zs += (lab4[b] == g) ? acc[rb][nf][4 * a + b] : 0.0f;
             }
         }
         zs += __shfl_xor(zs, 32);
-        if (half == 0 && cidx[nf] < NK) z[(item * P + pcol[nf]) * k + gcol[nf]] = zs;
+        const int64_t p = p_lo + slot0 / kLStride;
+        if (half == 0 && p < P) z[(item * P + p) * k + g] = zs;
     }
 }
 

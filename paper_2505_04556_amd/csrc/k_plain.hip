@@ -160,6 +160,93 @@ void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t
                        pl.P_pad, w, k, partial);
 }
 
+// ---- few groupings at FP64 (the tie recheck) ---------------------------------
+// With only a handful of groupings the lane-per-permutation form leaves most
+// lanes idle and re-walks each tile per lane.  Here the lanes run over pairs
+// instead: for each 64 x 64 tile of the triangle, each thread takes 16 of its
+// pairs (one column, every fourth row), holds their d^2 in FP64 registers, and
+// for each of EQ groupings adds the d^2 of its pairs whose two labels agree,
+// times that label's weight (Algorithm 1's sum, split by column).  D is read
+// once for all EQ groupings.  A work-group walks a contiguous run of tiles and
+// writes one partial per grouping; every sum has a fixed order (wave
+// shuffles, then per-wave running sums, then the four waves in order, then the
+// runs in order), so results are reproducible.
+constexpr int kFT = 64;               // tile edge
+constexpr int64_t kFewChunks = 4096;  // work-groups (tile runs) per launch
+constexpr int64_t kFewMaxM = 1024;    // groupings per launch
+
+template <int EQ>
+__global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, int64_t n,
+                                                int64_t nt, int64_t tiles, int64_t tpc,
+                                                const int32_t *__restrict__ g,
+                                                const int32_t *__restrict__ rows, int64_t m,
+                                                int32_t k, const double *__restrict__ w,
+                                                double *__restrict__ partial, int64_t m_pad) {
+    __shared__ int32_t sl[EQ][2][kFT];      // [grouping][rows, columns][64]
+    __shared__ double sred[4][EQ];
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, c = tid % 64;
+    const int64_t q0 = (int64_t)blockIdx.y * EQ;
+    if (tid < 4 * EQ) sred[tid / EQ][tid % EQ] = 0.0;
+    const int64_t t_end = ((int64_t)blockIdx.x + 1) * tpc < tiles ? ((int64_t)blockIdx.x + 1) * tpc
+                                                                  : tiles;
+    for (int64_t t = (int64_t)blockIdx.x * tpc; t < t_end; t++) {
+        int64_t I, J;
+        tri_decode(t, nt, I, J);
+        __syncthreads();   // the previous tile's labels are no longer read
+        // labels of this tile's rows and columns; padding never matches a column
+        for (int e = tid; e < EQ * 2 * kFT; e += 256) {
+            const int q = e / (2 * kFT), side = (e / kFT) % 2, x = e % kFT;
+            const int64_t idx = (side ? J : I) * kFT + x;
+            int32_t v = -1 - side;
+            if (q0 + q < m && idx < n) v = g[(int64_t)rows[q0 + q] * n + idx];
+            sl[q][side][x] = v;
+        }
+        const int64_t j = J * kFT + c;
+        double d2[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int64_t i = I * kFT + wave + 4 * u;
+            d2[u] = (j < n && i < j) ? square<double>(mat[i * n + j]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int q = 0; q < EQ; q++) {
+            const int32_t lc = sl[q][1][c];
+            const double wc = (lc >= 0 && lc < k) ? w[lc] : 0.0;
+            double sum = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; u++) sum += (sl[q][0][wave + 4 * u] == lc) ? d2[u] : 0.0;
+            double v = sum * wc;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+            if (c == 0) sred[wave][q] += v;
+        }
+    }
+    __syncthreads();
+    if (tid < EQ && q0 + tid < m)
+        partial[(int64_t)blockIdx.x * m_pad + q0 + tid] =
+            ((sred[0][tid] + sred[1][tid]) + sred[2][tid]) + sred[3][tid];
+}
+
+// out[q] = sum over runs, in a fixed order, of partial[run][q]: one
+// work-group per grouping, strided partial sums then a tree in LDS.
+__global__ __launch_bounds__(256) void k_reduce_few(const double *__restrict__ partial,
+                                                    int64_t runs, int64_t m_pad,
+                                                    double *__restrict__ out) {
+    __shared__ double sh[256];
+    const int64_t q = blockIdx.x;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < runs; t += 256) s += partial[t * m_pad + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = sh[0];
+}
+
 } // namespace
 
 PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu) {
@@ -206,6 +293,40 @@ void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int
     const int64_t gpad = round_up(max_units > 0 ? max_units : 1, 8);
     hipLaunchKernelGGL(k_plain_worklist, dim3((unsigned)gpad), dim3(kServeLanes), 0, s, jobs, units,
                        count);
+}
+
+} // namespace pstat
+
+namespace pstat {
+
+size_t few_partial_bytes(int64_t n, int64_t m) {
+    const int64_t nt = ceil_div(n, kFT);
+    const int64_t tiles = nt * (nt + 1) / 2;
+    const int64_t runs = tiles < kFewChunks ? tiles : kFewChunks;
+    const int64_t mm = m < kFewMaxM ? (m > 0 ? m : 1) : kFewMaxM;
+    return (size_t)runs * (size_t)round_up(mm, 8) * sizeof(double);
+}
+
+void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
+                   int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
+    const int64_t nt = ceil_div(n, kFT);
+    const int64_t tiles = nt * (nt + 1) / 2;
+    const int64_t runs = tiles < kFewChunks ? tiles : kFewChunks;
+    const int64_t tpc = ceil_div(tiles, runs);
+    const int64_t used = ceil_div(tiles, tpc);
+    for (int64_t b = 0; b < m; b += kFewMaxM) {
+        const int64_t mm = m - b < kFewMaxM ? m - b : kFewMaxM;
+        const int64_t m_pad = round_up(mm, 8);
+        if (mm <= 8)
+            hipLaunchKernelGGL(k_sw_few<8>, dim3((unsigned)used, 1), dim3(256), 0, s, mat, n, nt,
+                               tiles, tpc, g, rows + b, mm, k, w, partial, m_pad);
+        else
+            hipLaunchKernelGGL(k_sw_few<16>, dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
+                               dim3(256), 0, s, mat, n, nt, tiles, tpc, g, rows + b, mm, k, w,
+                               partial, m_pad);
+        hipLaunchKernelGGL(k_reduce_few, dim3((unsigned)mm), dim3(256), 0, s, partial, used, m_pad,
+                           out + b);
+    }
 }
 
 } // namespace pstat

@@ -179,20 +179,6 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
     return c.used + 256;
 }
 
-// Upper bound of sW_bytes over every P' <= P on a plain path (the plan's
-// chunk count depends on P', but chunks * P_pad stays below
-// (target + P/64 + 1) * 256).
-size_t plain_bytes_bound(int64_t n, int64_t P, int path) {
-    size_t b = 0;
-    for (int64_t q : {P, (int64_t)1, (int64_t)64, (int64_t)128, (int64_t)256})
-        if (q <= P) b = b > sW_bytes(n, q, 1, path, false) ? b : sW_bytes(n, q, 1, path, false);
-    const int64_t target = (int64_t)dev_info().n_cu * 32;
-    const size_t partial = (size_t)(target + P / 64 + 2) * 256 * sizeof(double);
-    const size_t labels = (size_t)round_up(n, 64) * round_up(P, 256) * sizeof(uint16_t);
-    const size_t bound = (size_t)P + partial + labels + 4 * 256;
-    return b > bound ? b : bound;
-}
-
 // Runs one evaluation: stage labels (row q of the staged problem is row
 // rows[q] of g, or row q when rows is NULL; rows is only used by plain paths),
 // run the kernel, reduce into out[0..P).  tiles: pre-squared tiles of a
@@ -332,15 +318,11 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
     int64_t rechecked = 0;
     if (path != PSTAT_PATH_PLAIN_F64) {
         const int64_t S = (n_perms < kBandSamples ? n_perms : kBandSamples) + 1;
+        if (region_bytes < few_partial_bytes(n, R)) return fail(PSTAT_ENOMEM, "recheck region too small");
+        double *partial = (double *)region;
         launch_iota(h.list, S, s);
-        {
-            Carver c{region, region_bytes, 0, false};
-            SwLayout L;
-            layout_sW(c, n, S, k, PSTAT_PATH_PLAIN_F64, true, L);
-            if ((rc = exec_sW(L, mat, n, h.allg, h.list, S, k, k, h.w, h.vals, nullptr, tls.flags,
-                              false)))
-                return rc;
-        }
+        launch_sw_few(mat, n, h.allg, h.list, S, k, h.w, partial, h.vals, s);
+        if ((rc = check_launch("FP64 recheck"))) return rc;
         launch_tie_band(h.sw, h.vals, S, kBandMargin, h.band, s);
         launch_scatter(h.vals, h.list, S, h.sw, s);
         if ((rc = check_launch("tie band"))) return rc;
@@ -355,14 +337,9 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
             m = tls.host_flags[2];
         }
         if (m > 0) {
-            Carver c{region, region_bytes, 0, false};
-            SwLayout L;
-            layout_sW(c, n, m, k, PSTAT_PATH_PLAIN_F64, true, L);
-            if ((rc = exec_sW(L, mat, n, h.allg, h.list, m, k, k, h.w, h.vals, nullptr, tls.flags,
-                              false)))
-                return rc;
+            launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s);
             launch_scatter(h.vals, h.list, m, h.sw, s);
-            if ((rc = check_launch("recheck scatter"))) return rc;
+            if ((rc = check_launch("recheck"))) return rc;
         }
         rechecked = S - 1 + m;
     }
@@ -581,9 +558,9 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     TestHead h;
     Carver dry{nullptr, 0, 0, true};
     carve_head(dry, n, R, k, h);
-    const size_t head = dry.used + 256;
+    const size_t head = (size_t)round_up((int64_t)dry.used, 256) + 256;
     size_t region = sW_bytes(n, R, k, path, true);
-    const size_t region64 = plain_bytes_bound(n, R, PSTAT_PATH_PLAIN_F64);
+    const size_t region64 = few_partial_bytes(n, R);
     if (region64 > region) region = region64;
     char *ws;
     if ((rc = acquire_workspace(head + region, &ws))) return rc;

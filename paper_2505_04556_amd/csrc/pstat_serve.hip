@@ -374,7 +374,7 @@ int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all
     else
         launch_reduce_mfma(J.z, J.mp.items, R, J.k, J.head.w, J.bad, J.tmp, J.head.sw, s);
     if ((rc = check_launch("job reduce"))) return rc;
-    const size_t region = plain_bytes_bound(J.n, R, PSTAT_PATH_PLAIN_F64);
+    const size_t region = few_partial_bytes(J.n, R);
     char *ws;
     if ((rc = acquire_workspace(region, &ws))) return rc;
     int64_t rechecked = 0;

@@ -102,7 +102,6 @@ struct SwLayout {
 void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
                SwLayout &L);
 size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles);
-size_t plain_bytes_bound(int64_t n, int64_t P, int path);
 
 // Event pair around the main kernel when this thread is profiling.
 struct KernelTimer {
@@ -151,7 +150,7 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
                  int64_t n_perms, uint64_t seed, int32_t max_label);
 // After h.sw holds the fast path's s_W of all R rows: s_T, FP64 recheck of the
 // observed grouping, band samples and near ties, p-value, result.  `region` is
-// scratch of at least plain_bytes_bound(n, R, PSTAT_PATH_PLAIN_F64) bytes.
+// scratch of at least few_partial_bytes(n, R) bytes.
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked);
 
