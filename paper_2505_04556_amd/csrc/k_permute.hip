@@ -9,10 +9,21 @@
 // Lemire's multiply-shift with rejection (ACM TOMACS 2019): m = x * s,
 // accept when the low 32 bits of m are >= (2^32 - s) mod s, return m >> 32.
 //
-// Each lane shuffles one permutation.  When n labels of the narrowest type
-// that holds them fit in LDS, a work-group of one wave keeps up to 64 arrays
-// in LDS (random swaps then cost LDS latency, not HBM latency) and writes the
-// finished rows out coalesced; otherwise lanes shuffle in place in the output.
+// Batched form (used whenever a few arrays fit in LDS).  Draw d of a stream is
+// hi32(mix(start + (d + 1) * gamma)), so any draw can be computed on its own.
+// A wave holds 64 / B arrays in LDS and advances each by B steps per batch:
+// lane t of a permutation's group computes draw d + t, the step it would
+// serve if no draw of the batch is rejected (top index i - t, bound i - t + 1)
+// and its swap partner j_t.  When no draw is rejected and the B swaps touch
+// pairwise different positions (no j_t falls on another step's top index or
+// on another j), the swaps commute and the group performs them in parallel:
+// one LDS round trip instead of B.  Otherwise the group's first lane replays
+// the batch's draws in order -- exactly the sequential algorithm, rejections
+// included.  Each batch consumes B draws per permutation either way, so the
+// result is bit-identical to the one-lane-per-permutation form.
+//
+// Fallbacks: one lane per permutation with the arrays in LDS, or in place in
+// the output when not even one array fits.
 #include "internal.h"
 
 namespace pstat {
@@ -65,6 +76,171 @@ __device__ inline void shuffle(E *a, int64_t n, uint64_t seed, int64_t p) {
         a[i] = aj;
         a[j] = ai;
         j = jn;
+    }
+}
+
+// Value of lane (t + r) mod B of this lane's group of B lanes: a row
+// rotation (DPP, no LDS round trip) when the group is one 16-lane row.
+template <int B>
+__device__ inline uint32_t rotate_in_group(uint32_t v, int r, int gbase, int t) {
+    if constexpr (B == 16) {
+        // row_ror:r moves lane l's value to lane l + r (mod 16): read the other
+        // direction, 16 - r
+        switch (r) {
+#define PSTAT_ROR(R_) case R_: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + (16 - R_) % 16, 0xF, 0xF, false);
+        PSTAT_ROR(1) PSTAT_ROR(2) PSTAT_ROR(3) PSTAT_ROR(4) PSTAT_ROR(5) PSTAT_ROR(6) PSTAT_ROR(7)
+        PSTAT_ROR(8) PSTAT_ROR(9) PSTAT_ROR(10) PSTAT_ROR(11) PSTAT_ROR(12) PSTAT_ROR(13) PSTAT_ROR(14)
+        PSTAT_ROR(15)
+#undef PSTAT_ROR
+        }
+        return v;
+    } else {
+        return (uint32_t)__shfl((int)v, gbase + (t + r) % B);
+    }
+}
+
+// Batched shuffle: B lanes per permutation, 64 / B permutations per wave,
+// blockDim.x / 64 waves per work-group, arrays in dynamic LDS.
+template <typename E, int B>
+__global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict__ base, int64_t n,
+                                                       int64_t P, uint64_t seed, int vec,
+                                                       int32_t *__restrict__ out) {
+    constexpr int PW = 64 / B;
+    extern __shared__ __align__(16) unsigned char smem[];
+    E *arr = reinterpret_cast<E *>(smem);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int ppg = (nthr / 64) * PW;                 // permutations per work-group
+    const int64_t p0 = (int64_t)blockIdx.x * ppg;
+    int live = ppg;
+    if (p0 + live > P) live = (int)(P - p0);
+    // copy in (as in the one-lane form)
+    const int64_t n4 = vec ? n / 4 : 0;
+    const int4 *base4 = reinterpret_cast<const int4 *>(base);
+    for (int64_t v = tid; v < n4; v += nthr) {
+        const int4 b = base4[v];
+        for (int q = 0; q < live; q++) {
+            E *d = arr + (int64_t)q * n + 4 * v;
+            d[0] = (E)b.x;
+            d[1] = (E)b.y;
+            d[2] = (E)b.z;
+            d[3] = (E)b.w;
+        }
+    }
+    for (int64_t i = 4 * n4 + tid; i < n; i += nthr) {
+        const E b = (E)base[i];
+        for (int q = 0; q < live; q++) arr[(int64_t)q * n + i] = b;
+    }
+    __syncthreads();
+
+    const int wave = tid / 64, lane = tid % 64;
+    const int ps = lane / B, t = lane % B;          // permutation slot in the wave, lane in group
+    const int slot = wave * PW + ps;
+    const bool mine = slot < live;
+    const int gbase = (lane / B) * B;               // first lane of the group
+    E *a = arr + (int64_t)(mine ? slot : 0) * n;
+    const uint64_t start = stream_start(seed, (uint64_t)(p0 + slot));
+    int64_t top = mine ? n - 1 : 0;                 // current i of the permutation
+    // one private LDS slot per thread after the arrays: the target of the
+    // swap of a lane with nothing to swap, so the swap needs no branch
+    E *const dummy = arr + (int64_t)ppg * n + tid;
+    uint32_t x = (uint32_t)(mix64(start + ((uint64_t)t + 1) * kGamma) >> 32);
+    for (uint64_t d = 0;; d += B) {
+        // the wave runs until all of its permutations are done
+        if (__ballot(top >= 1) == 0) break;
+        const int64_t it = top - t;                  // this lane's step if nothing is rejected
+        const bool valid = it >= 1;
+        const uint32_t sb = (uint32_t)(it + 1);
+        const uint64_t m = (uint64_t)x * (uint64_t)sb;
+        const uint32_t lo = (uint32_t)m;
+        const int64_t j = (int64_t)(m >> 32);
+        bool ok = true;
+        if (valid && lo < sb) ok = lo >= (uint32_t)(0u - sb) % sb;
+        const uint64_t gmask = (B == 64) ? ~0ull : (((1ull << B) - 1) << gbase);
+        // A rejected draw shifts every later step of the batch onto another
+        // draw: such a group replays the batch in order (rare).
+        const bool grej = (__ballot(valid && !ok) & gmask) != 0;
+        // Conflicts: a swap whose partner is another step's top index, two
+        // swaps with the same partner, or a step whose top is some other
+        // step's partner.  Swaps without conflict commute with every other
+        // swap of the batch; the conflicting ones keep their order.
+        const bool real = valid && j != it;
+        int64_t lowtop = top - B + 1;
+        if (lowtop < 1) lowtop = 1;
+        bool conflict = real && j >= lowtop && j < it;
+        // Every other lane's partner key (idle lanes and self-swaps carry ~t,
+        // which no partner or top index equals): two equal partners, or a
+        // partner on this lane's top index.
+        const uint32_t key = real ? (uint32_t)j : ~(uint32_t)t;
+#pragma unroll
+        for (int r = 1; r < B; r++) {
+            const uint32_t ko = rotate_in_group<B>(key, r, gbase, t);
+            if ((real && ko == key) || ko == (uint32_t)it) conflict = true;
+        }
+        conflict = conflict && valid;
+
+        // swaps without conflict, all at once; the next batch's draw is
+        // computed while they are in flight
+        {
+            const bool now = valid && !conflict && mine && !grej;
+            E *pa = now ? a + it : dummy;
+            E *pb = now ? a + j : dummy;
+            const E va = *pa, vb = *pb;
+            *pa = vb;
+            *pb = va;
+        }
+        const uint32_t xn = (uint32_t)(mix64(start + (d + B + (uint64_t)t + 1) * kGamma) >> 32);
+
+        if (__ballot(grej) != 0) {
+            // gather the group's draws into its first lane, all lanes active
+            uint32_t xs[B];
+#pragma unroll
+            for (int r = 0; r < B; r++) xs[r] = __shfl(x, gbase + r);
+            if (grej && t == 0 && mine) {
+                int64_t i = top;
+#pragma unroll
+                for (int r = 0; r < B; r++) {
+                    if (i >= 1) {
+                        const uint32_t sr = (uint32_t)(i + 1);
+                        const uint64_t mr = (uint64_t)xs[r] * (uint64_t)sr;
+                        const uint32_t lr = (uint32_t)mr;
+                        // a rejected draw is consumed and the step keeps its bound
+                        if (!(lr < sr && lr < (uint32_t)(0u - sr) % sr)) {
+                            const int64_t jr = (int64_t)(mr >> 32);
+                            const E ai = a[i], aj = a[jr];
+                            a[i] = aj;
+                            a[jr] = ai;
+                            --i;
+                        }
+                    }
+                }
+                top = i;
+            }
+            top = __shfl(top, gbase);
+        }
+        // then the conflicting swaps of each group, lowest step first
+        uint64_t cm = __ballot(conflict && mine && !grej);
+        while (cm != 0) {
+            const uint64_t g = cm & gmask;
+            const bool turn = g != 0 && lane == __builtin_ctzll(g);
+            if (turn) {
+                const E ai = a[it], aj = a[j];
+                a[it] = aj;
+                a[j] = ai;
+            }
+            cm &= ~__ballot(turn);
+        }
+        if (!grej) top = top - B < 0 ? 0 : top - B;
+        x = xn;
+    }
+    __syncthreads();
+    // copy out
+    for (int q = 0; q < live; q++) {
+        const E *src = arr + (int64_t)q * n;
+        int32_t *dst = out + (p0 + q) * n;
+        int4 *dst4 = reinterpret_cast<int4 *>(dst);
+        for (int64_t v = tid; v < n4; v += nthr)
+            dst4[v] = make_int4(src[4 * v], src[4 * v + 1], src[4 * v + 2], src[4 * v + 3]);
+        for (int64_t i = 4 * n4 + tid; i < n; i += nthr) dst[i] = (int32_t)src[i];
     }
 }
 
@@ -139,11 +315,53 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
     return 0;
 }
 
+// Batched form: up to four waves per work-group (one per SIMD) sharing the
+// arrays that fit; each wave takes PW = 64 / B of them, PW the largest power
+// of two with four waves' worth of arrays (at most 8, at least 1).
+template <typename E>
+int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t *out,
+                 size_t lds_limit, hipStream_t s) {
+    const size_t row = (size_t)n * sizeof(E);
+    const size_t spare = 256 * sizeof(E);        // the per-thread dummy slots
+    if (lds_limit <= spare) return 1;
+    const int64_t fit = (int64_t)((lds_limit - spare) / row);
+    if (fit < 1) return 1;
+    int pw = 1;
+    while (pw < 8 && 2 * pw * 4 <= fit) pw *= 2;
+    const int B = 64 / pw;
+    int64_t waves = fit / pw;
+    if (waves > 4) waves = 4;
+    // no more waves than the permutations need
+    while (waves > 1 && (waves - 1) * pw >= P) --waves;
+    const int64_t ppg = waves * pw;
+    const size_t bytes = (size_t)ppg * row + spare;
+    const int64_t blocks = ceil_div(P, ppg);
+    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    const dim3 grid((unsigned)blocks), block((unsigned)(64 * waves));
+#define PSTAT_BATCH_CASE(B_)                                                                     \
+    if (B == B_) {                                                                               \
+        (void)hipFuncSetAttribute((const void *)k_permute_batch<E, B_>,                          \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);       \
+        hipLaunchKernelGGL((k_permute_batch<E, B_>), grid, block, bytes, s, base, n, P, seed, vec, \
+                           out);                                                                 \
+        return 0;                                                                                \
+    }
+    PSTAT_BATCH_CASE(8)
+    PSTAT_BATCH_CASE(16)
+    PSTAT_BATCH_CASE(32)
+    PSTAT_BATCH_CASE(64)
+#undef PSTAT_BATCH_CASE
+    return 1;
+}
+
 } // namespace
 
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
                    int32_t *out, size_t lds_limit, hipStream_t s) {
     if (P <= 0 || n <= 0) return 0;
+    if (max_label < 256 && launch_batch<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
+    if (max_label < 65536 && launch_batch<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)
+        return 0;
     if (max_label < 256 && launch_lds<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
     if (max_label < 65536 && launch_lds<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)
         return 0;

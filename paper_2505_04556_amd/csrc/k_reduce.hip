@@ -28,16 +28,24 @@ __global__ void k_reduce_plain(const double *__restrict__ partial, int64_t chunk
     }
 }
 
-// tmp[p][g] = sum over items, ascending, of z[item][p][g] (FP32 -> FP64).
-__global__ void k_reduce_items(const float *__restrict__ z, int64_t items, int64_t P,
-                               int32_t k, double *__restrict__ tmp) {
+// tmp[p][g] = sum over items of z[item][p][g] (FP32 -> FP64) in a fixed
+// order: thread (e, r) of a 64 x 4 block adds items r, r + 4, ... ascending;
+// the four slices are then added in order.
+__global__ __launch_bounds__(256) void k_reduce_items(const float *__restrict__ z, int64_t items,
+                                                      int64_t P, int32_t k,
+                                                      double *__restrict__ tmp) {
+    __shared__ double part[4][64];
     const int64_t total = P * k;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int64_t it = 0; it < items; it++) s += (double)z[it * total + e];
-        tmp[e] = s;
+    const int el = threadIdx.x % 64, r = threadIdx.x / 64;
+    const int64_t e = (int64_t)blockIdx.x * 64 + el;
+    double s = 0.0;
+    if (e < total) {
+#pragma unroll 4
+        for (int64_t it = r; it < items; it += 4) s += (double)z[it * total + e];
     }
+    part[r][el] = s;
+    __syncthreads();
+    if (r == 0 && e < total) tmp[e] = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
 }
 
 // out[p] = sum over g ascending of w[g] * tmp[p][g].
@@ -148,8 +156,8 @@ void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, i
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
                         const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s) {
     if (P <= 0) return;
-    hipLaunchKernelGGL(k_reduce_items, dim3(blocks_for(P * k, 256)), dim3(256), 0, s, z, items,
-                       P, k, tmp);
+    hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(P * k, 64)), dim3(256), 0, s, z,
+                       items, P, k, tmp);
     hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
                        bad_perm, out);
 }

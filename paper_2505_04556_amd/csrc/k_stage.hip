@@ -62,6 +62,32 @@ __global__ __launch_bounds__(256) void k_stage_labels_pm(
     }
 }
 
+// Same, four labels per thread (16-byte loads, 8-byte stores) when n % 4 == 0
+// and g is 16-byte aligned.
+__global__ __launch_bounds__(256) void k_stage_labels_pm4(
+    const int32_t *__restrict__ g, int64_t n, int64_t P, int64_t n_pad, int64_t P_pad,
+    int32_t limit, uint16_t *__restrict__ out, uint8_t *__restrict__ bad_perm,
+    int32_t *__restrict__ err_flag) {
+    const int64_t q_pad = n_pad / 4;
+    for (int64_t p = blockIdx.y; p < P_pad; p += gridDim.y) {
+        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < q_pad;
+             q += (int64_t)gridDim.x * 256) {
+            const int64_t i = 4 * q;
+            uint16_t v[4] = {kPadLabel, kPadLabel, kPadLabel, kPadLabel};
+            if (p < P && i < n) {
+                const int4 x = *reinterpret_cast<const int4 *>(g + p * n + i);
+                v[0] = check_label(x.x, limit, p, bad_perm, err_flag);
+                v[1] = check_label(x.y, limit, p, bad_perm, err_flag);
+                v[2] = check_label(x.z, limit, p, bad_perm, err_flag);
+                v[3] = check_label(x.w, limit, p, bad_perm, err_flag);
+            }
+            *reinterpret_cast<uint2 *>(out + p * n_pad + i) =
+                make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16),
+                           (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+        }
+    }
+}
+
 // Flat range check and maximum of int32 labels.
 __global__ __launch_bounds__(256) void k_scan_labels(const int32_t *__restrict__ g, int64_t count,
                                                      int32_t limit, int32_t *__restrict__ err_flag,
@@ -103,13 +129,29 @@ __global__ void k_zero_u32(uint32_t *p, int64_t count) {
         p[i] = 0u;
 }
 
-__global__ void k_count_groups(const int32_t *__restrict__ grouping, int64_t n, int32_t k,
-                               uint32_t *__restrict__ counts) {
+// Group sizes: per-block histogram in LDS (k <= kHist), then one global
+// atomic per non-empty bin; larger k counts with global atomics directly.
+constexpr int kHist = 4096;
+__global__ __launch_bounds__(256) void k_count_groups(const int32_t *__restrict__ grouping,
+                                                      int64_t n, int32_t k,
+                                                      uint32_t *__restrict__ counts) {
+    __shared__ uint32_t hist[kHist];
+    const bool local = k <= kHist;
+    if (local)
+        for (int g = threadIdx.x; g < k; g += blockDim.x) hist[g] = 0;
+    __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = grouping[i];
-        if (v >= 0 && v < k) atomicAdd(&counts[v], 1u);
+        if (v >= 0 && v < k) {
+            if (local) atomicAdd(&hist[v], 1u);
+            else atomicAdd(&counts[v], 1u);
+        }
     }
+    __syncthreads();
+    if (local)
+        for (int g = threadIdx.x; g < k; g += blockDim.x)
+            if (hist[g]) atomicAdd(&counts[g], hist[g]);
 }
 
 __global__ void k_invert_counts(const uint32_t *__restrict__ counts, int32_t k,
@@ -142,13 +184,21 @@ __global__ __launch_bounds__(256) void k_sT_partial(const float *__restrict__ ma
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ void k_sT_final(const double *__restrict__ partials, int64_t count, int64_t n,
-                           double *__restrict__ sT) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int64_t b = 0; b < count; b++) s += partials[b];
-        *sT = s / (double)n;
+// s_T = (sum of the partials) / n: thread t adds partials t, t + 256, ...
+// ascending, then a fixed-shape tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_sT_final(const double *__restrict__ partials,
+                                                  int64_t count, int64_t n,
+                                                  double *__restrict__ sT) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < count; b += 256) s += partials[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *sT = red[0] / (double)n;
 }
 
 inline unsigned grid_for(int64_t count, int block, int64_t cap = 65535) {
@@ -178,6 +228,12 @@ void launch_scan_labels(const int32_t *g, int64_t count, int32_t limit, int32_t 
 void launch_stage_labels_pm(const int32_t *g, int64_t n, int64_t P, int64_t n_pad,
                             int64_t P_pad, int32_t limit, uint16_t *out, uint8_t *bad_perm,
                             int32_t *err_flag, hipStream_t s) {
+    if (n % 4 == 0 && n_pad % 4 == 0 && (uintptr_t)g % 16 == 0 && (uintptr_t)out % 8 == 0) {
+        dim3 grid(grid_for(n_pad / 4, 256, 64), (unsigned)(P_pad < 65535 ? P_pad : 65535));
+        hipLaunchKernelGGL(k_stage_labels_pm4, grid, dim3(256), 0, s, g, n, P, n_pad, P_pad, limit,
+                           out, bad_perm, err_flag);
+        return;
+    }
     dim3 grid(grid_for(n_pad, 256, 64), (unsigned)(P_pad < 65535 ? P_pad : 65535));
     hipLaunchKernelGGL(k_stage_labels_pm, grid, dim3(256), 0, s, g, n, P, n_pad, P_pad, limit,
                        out, bad_perm, err_flag);
@@ -197,7 +253,7 @@ void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_
                           double *inv, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(k, 256, 4096)), dim3(256), 0, s, counts,
                        (int64_t)k);
-    hipLaunchKernelGGL(k_count_groups, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, grouping,
+    hipLaunchKernelGGL(k_count_groups, dim3(grid_for(n, 256, 256)), dim3(256), 0, s, grouping,
                        n, k, counts);
     hipLaunchKernelGGL(k_invert_counts, dim3(grid_for(k, 256)), dim3(256), 0, s, counts, k, inv);
 }
@@ -207,7 +263,7 @@ int64_t sT_partials_count(int64_t n) { return n - 1 < kSTBlocks ? (n > 1 ? n - 1
 void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s) {
     const int64_t blocks = sT_partials_count(n);
     hipLaunchKernelGGL(k_sT_partial, dim3((unsigned)blocks), dim3(256), 0, s, mat, n, partials);
-    hipLaunchKernelGGL(k_sT_final, dim3(1), dim3(64), 0, s, partials, blocks, n, sT);
+    hipLaunchKernelGGL(k_sT_final, dim3(1), dim3(256), 0, s, partials, blocks, n, sT);
 }
 
 } // namespace pstat
