@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_bounded.argtypes = [P, ctypes.c_uint32]
         L.oracle_bounded.restype = ctypes.c_uint32
         L.oracle_permute.argtypes = [P, i64, i64, u64, P, c_int]
+        L.oracle_count_rejections.argtypes = [i64, i64, u64]
+        L.oracle_count_rejections.restype = i64
         L.oracle_max_threads.restype = c_int
         _lib = L
     return _lib
@@ -182,6 +184,12 @@ def permute(base, n_perms: int, seed: int, nthreads: int = 0) -> np.ndarray:
     out = np.empty((n_perms, base.shape[0]), dtype=np.int32)
     lib().oracle_permute(_ptr(base), base.shape[0], n_perms, seed, _ptr(out), nthreads)
     return out
+
+
+def count_rejections(n: int, n_perms: int, seed: int) -> int:
+    """Draws discarded by the bounded draws of permute(base of length n, ...)
+    (test helper: which inputs exercise a generator's rejection path)."""
+    return int(lib().oracle_count_rejections(int(n), int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF))
 
 
 def group_sizes(grouping, k: int | None = None) -> np.ndarray:

@@ -217,6 +217,26 @@ uint32_t oracle_bounded(uint64_t *state, uint32_t s) {
     return (uint32_t)(m >> 32);
 }
 
+/* Test helper: number of draws the bounded draws of oracle_permute discard
+ * (Lemire rejections) over n_perms shuffles of n labels -- which inputs
+ * exercise a generator's rejection path. */
+int64_t oracle_count_rejections(int64_t n, int64_t n_perms, uint64_t seed) {
+    int64_t total = 0;
+    for (int64_t p = 0; p < n_perms; p++) {
+        uint64_t st = oracle_stream_start(seed, (uint64_t)p);
+        for (int64_t i = n - 1; i >= 1; i--) {
+            const uint32_t s = (uint32_t)(i + 1);
+            for (;;) {
+                const uint32_t x = (uint32_t)(oracle_splitmix64_next(&st) >> 32);
+                const uint32_t l = (uint32_t)((uint64_t)x * (uint64_t)s);
+                if (l >= s || l >= (uint32_t)(-s) % s) break;
+                total++;
+            }
+        }
+    }
+    return total;
+}
+
 /* groupings[p*n + i]: Fisher-Yates (Durstenfeld, i from n-1 down to 1, swap
  * with a uniform j in [0, i]) applied to a copy of base, stream of perm p. */
 void oracle_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed,

@@ -37,6 +37,13 @@ __device__ inline void tri_decode(int64_t t, int64_t nt, int64_t &I, int64_t &J)
 }
 
 template <typename Acc>
+struct VecOf;
+template <>
+struct VecOf<float> { using type = float4; };
+template <>
+struct VecOf<double> { using type = double2; };
+
+template <typename Acc>
 __device__ inline Acc square(float d);
 template <>
 __device__ inline float square<float>(float d) { return d * d; }
@@ -55,6 +62,7 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int6
     const int tid = threadIdx.x;
     const int64_t perm = pg * LANES + tid;
     const int kc = k < kWeightCache ? k : kWeightCache;
+    const bool wlds = k <= kWeightCache;   // uniform: every weight in LDS
     for (int g = tid; g < kc; g += LANES) sWt[g] = w[g];
 
     const int64_t t0 = chunk * tiles_per_chunk;
@@ -88,9 +96,14 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int6
                 const int e = tid + q * LANES;
                 sD[e / T][e % T] = square<Acc>(pre[q]);
             }
-            uint32_t Lc[T];
+            // this lane's labels of the tile's columns and rows
+            uint32_t Lc[T], Li[T];
 #pragma unroll
             for (int c = 0; c < T; c++) Lc[c] = lab[(j0 + c) * P_pad + perm];
+#pragma unroll
+            for (int r = 0; r < T; r++) Li[r] = lab[(i0 + r) * P_pad + perm];
+#pragma unroll
+            for (int c = 0; c < T; c++) asm volatile("" : "+v"(Lc[c]));
             __syncthreads();
             // Next tile's global loads overlap this tile's arithmetic.
             int64_t In = I, Jn = J + 1;
@@ -98,12 +111,38 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int6
             if (t + 1 < t1) fetch(In, Jn);
 #pragma unroll 2
             for (int r = 0; r < T; r++) {
-                const uint32_t li = lab[(i0 + r) * P_pad + perm];
+                uint32_t li = Li[r];
+                // The row's d^2 come in as 16-byte broadcast reads, all of
+                // them, before any select (left alone, the compiler predicates
+                // each LDS read on its label test); the empty asm statements
+                // pin that, and make the label compares plain 32-bit ones.
+                constexpr int V = 16 / sizeof(Acc);
+                using Vec = typename VecOf<Acc>::type;
+                const Vec *row = reinterpret_cast<const Vec *>(
+                    __builtin_assume_aligned(&sD[r][0], 16));
+                Acc d[T];
+#pragma unroll
+                for (int c4 = 0; c4 < T / V; c4++) {
+                    const Vec v = row[c4];
+                    __builtin_memcpy(&d[c4 * V], &v, sizeof(Vec));
+                }
+#pragma unroll
+                for (int c = 0; c < T; c++) asm volatile("" : "+v"(d[c]));
+                asm volatile("" : "+v"(li));
                 Acc acc = Acc(0);
 #pragma unroll
-                for (int c = 0; c < T; c++) acc += (li == Lc[c]) ? sD[r][c] : Acc(0);
+                for (int c = 0; c < T; c++) acc += (li == Lc[c]) ? d[c] : Acc(0);
+                // weights from LDS (k <= kWeightCache), else from global memory;
+                // padding rows (label kPadLabel >= k) weigh 0
                 double wv = 0.0;
-                if ((int32_t)li < k) wv = ((int32_t)li < kWeightCache) ? sWt[li] : w[li];
+                if (wlds) {
+                    // an LDS pointer, so the load stays an LDS read
+                    const __attribute__((address_space(3))) double *sw =
+                        (const __attribute__((address_space(3))) double *)sWt;
+                    if (li < (uint32_t)k) wv = sw[li];
+                } else {
+                    if (li < (uint32_t)k) wv = w[li];
+                }
                 tot += (double)acc * wv;
             }
             I = In;
@@ -128,7 +167,7 @@ __global__ __launch_bounds__(LANES) void k_plain(
     double *__restrict__ partial) {
     const int64_t logical = xcd_logical(blockIdx.x, gridDim.x);
     if (logical >= grid_real) return;
-    __shared__ Acc sD[T][T];
+    __shared__ __align__(16) Acc sD[T][T];
     __shared__ double sWt[kWeightCache];
     plain_unit<T, LANES, Acc>(mat, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
                               logical / pgroups, logical % pgroups, sD, sWt);
@@ -143,7 +182,7 @@ __global__ __launch_bounds__(kServeLanes) void k_plain_worklist(
     if (logical >= *count) return;
     const UnitDesc u = units[logical];
     const JobDesc j = jobs[u.job];
-    __shared__ float sD[kServeTile][kServeTile];
+    __shared__ __align__(16) float sD[kServeTile][kServeTile];
     __shared__ double sWt[kWeightCache];
     plain_unit<kServeTile, kServeLanes, float>(j.mat, j.n, j.nt, j.n_tiles, j.tiles_per_chunk,
                                                j.lab, j.P_pad, j.w, j.k, j.partial, u.chunk,
