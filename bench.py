@@ -91,6 +91,35 @@ def time_path(ps, torch, path, D, base, cfg, steps, warmup, tuning=None):
                 result=res.cpu().numpy())
 
 
+def speedup_leg(ps, torch, sd, synth, steps=3, warmup=1):
+    """The precision workload (n=25,000, k=10 uneven groups, 3,999
+    permutations): whole tests on the plain FP32 and split-BF16 forms with the
+    library defaults; the split form's speedup over the plain one."""
+    cfg = synth.config(2)
+    D = sd.matrix(cfg)
+    base = torch.from_numpy(synth.base_labels(cfg["sizes"])).cuda()
+    n, P = cfg["n"], cfg["n_perms"]
+    pair_perms = n * (n - 1) // 2 * P
+    res = {}
+    for path in ("plain_f32", "mfma_split_bf16"):
+        r = time_path(ps, torch, path, D, base, cfg, steps, warmup)
+        res[path] = dict(ms_per_step=round(r["ms_per_step"], 3),
+                         kernel_ms=round(r["kernel_ms_total"] / max(1, r["kernel_launches"]), 3),
+                         G_pair_perms_per_s=round(pair_perms / (r["ms_per_step"] / 1e3) / 1e9, 1),
+                         F_obs=float(r["result"][0]), p=float(r["result"][1]))
+    ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
+    del D
+    torch.cuda.empty_cache()
+    return dict(workload=cfg["name"], steps=steps, forms=res,
+                speedup_whole_test=round(res["plain_f32"]["ms_per_step"]
+                                         / res["mfma_split_bf16"]["ms_per_step"], 3),
+                speedup_kernel=round(res["plain_f32"]["kernel_ms"]
+                                     / res["mfma_split_bf16"]["kernel_ms"], 3),
+                rel_err_bound=1e-5,
+                rel_err_checked_by="tests/test_gpu_fullsize.py::test_n25000_precision_table "
+                                   "(every permutation against the FP64 oracle)")
+
+
 def cpu_baseline(D_host, cfg, target_s=12.0):
     """The FP64 oracle, as it stands, on this host's cores over a bounded
     sample of the same workload's permutations."""
@@ -178,6 +207,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuning")
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the n=25,000 plain-vs-split-BF16 comparison")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -234,6 +265,12 @@ def main() -> int:
         cpu = cpu_baseline(D.cpu().numpy(), cfg)
         log(f"  oracle: {cpu['value']:.3f} G pair-perms/s on {cpu['threads']} threads, "
             f"{cpu['perms']} perms in {cpu['seconds']:.1f} s")
+
+    speedup = None
+    if not args.no_speedup:
+        log("speedup leg: n=25,000, k=10, 3,999 permutations, plain FP32 vs split BF16")
+        speedup = speedup_leg(ps, torch, sd, synth)
+        log(f"  {speedup}")
 
     serve = None
     if not args.no_serve:
@@ -304,6 +341,8 @@ def main() -> int:
                       "max_rel_err_vs_oracle_sample": acc.get(p)}
                   for p, v in runs.items()},
     }
+    if speedup is not None:
+        out["speedup_n25000"] = speedup
     if serve is not None:
         out["serve"] = serve
     if cpu is not None:
