@@ -4,6 +4,8 @@ marshalling only).  Small and ragged sizes that span several tiles, plus the
 degenerate cases; the full workloads are in test_gpu_fullsize.py."""
 import ctypes
 
+import os
+
 import numpy as np
 import pytest
 
@@ -292,6 +294,35 @@ def test_group_weights(ps):
     g = np.array([0, 2, 2, 1, 2, 0, 4], dtype=np.int32)
     got = ps.pstat_group_weights(torch.from_numpy(g).cuda(), 5).cpu().numpy()
     assert np.array_equal(got, [0.5, 1.0, 1 / 3, 0.0, 1.0])
+
+
+def test_precision_table_n1000(ps):
+    """Per-form error against the FP64 oracle on the n=1000 uniform workload
+    (k=4, 999 permutations): every s_W of every form before any recheck."""
+    import json
+    import torch
+    cfg = synth.config(0)
+    D = synth.host_matrix(cfg)
+    base = synth.base_labels(cfg["sizes"])
+    P, seed, k = cfg["n_perms"], cfg["perm_seed"], cfg["k"]
+    perms = oracle.permute(base, P, seed)
+    rows = np.vstack([base, perms])
+    w = synth.inv_group_sizes(cfg["sizes"])
+    ref = oracle.sW(D, rows, w)
+    Dd, gd, wd = to_dev(D, rows, w)
+    table = {}
+    for path in ("plain_f64", "plain_f32", "mfma_split_bf16", "mfma_f16", "mfma_bf16"):
+        ps.pstat_set_path(path)
+        got = ps.pstat_sW_k(Dd, gd, k, wd).cpu().numpy()
+        table[path] = dict(max_rel_sW=max_rel(got, ref),
+                           mean_rel_sW=float(np.mean(np.abs(got - ref) / ref)))
+        assert max_rel(got, ref) <= TOL[path], (path, table[path])
+    ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "precision_n1000.json"), "w") as f:
+            json.dump(table, f, indent=1)
+    print("n1000", json.dumps(table), flush=True)
 
 
 @pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_bf16"])
