@@ -79,37 +79,44 @@ __device__ inline void shuffle(E *a, int64_t n, uint64_t seed, int64_t p) {
     }
 }
 
-// Value of lane (t + r) mod B of this lane's group of B lanes: a row
-// rotation (DPP, no LDS round trip) when the group is one 16-lane row.
-template <int B>
-__device__ inline uint32_t rotate_in_group(uint32_t v, int r, int gbase, int t) {
-    if constexpr (B == 16) {
-        // row_ror:r moves lane l's value to lane l + r (mod 16): read the other
-        // direction, 16 - r
-        switch (r) {
-#define PSTAT_ROR(R_) case R_: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + (16 - R_) % 16, 0xF, 0xF, false);
-        PSTAT_ROR(1) PSTAT_ROR(2) PSTAT_ROR(3) PSTAT_ROR(4) PSTAT_ROR(5) PSTAT_ROR(6) PSTAT_ROR(7)
-        PSTAT_ROR(8) PSTAT_ROR(9) PSTAT_ROR(10) PSTAT_ROR(11) PSTAT_ROR(12) PSTAT_ROR(13) PSTAT_ROR(14)
-        PSTAT_ROR(15)
+// Value of lane (t + r) mod 16 of this lane's 16-lane row (DPP row rotation,
+// no LDS round trip).
+__device__ inline uint32_t rotate_row(uint32_t v, int r) {
+    // row_ror:R moves lane l's value to lane l + R (mod 16): read the other
+    // direction, 16 - r
+    switch (r) {
+#define PSTAT_ROR(R_) case R_: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x120 + (16 - R_) % 16, 0xF, 0xF, true);
+    PSTAT_ROR(1) PSTAT_ROR(2) PSTAT_ROR(3) PSTAT_ROR(4) PSTAT_ROR(5) PSTAT_ROR(6) PSTAT_ROR(7)
+    PSTAT_ROR(8) PSTAT_ROR(9) PSTAT_ROR(10) PSTAT_ROR(11) PSTAT_ROR(12) PSTAT_ROR(13) PSTAT_ROR(14)
+    PSTAT_ROR(15)
 #undef PSTAT_ROR
-        }
-        return v;
-    } else {
-        return (uint32_t)__shfl((int)v, gbase + (t + r) % B);
     }
+    return v;
+}
+
+// The whole wave rotated by one lane (DPP wave_ror:1).
+__device__ inline uint32_t rotate_wave1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+}
+
+// The ballot bits of this lane's group of B lanes.
+template <int B>
+__device__ inline uint64_t group_mask(int gbase) {
+    if constexpr (B == 64) return ~0ull;
+    else return ((1ull << B) - 1) << gbase;
 }
 
 // Batched shuffle: B lanes per permutation, 64 / B permutations per wave,
 // blockDim.x / 64 waves per work-group, arrays in dynamic LDS.
 template <typename E, int B>
 __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict__ base, int64_t n,
-                                                       int64_t P, uint64_t seed, int vec,
+                                                       int64_t P, uint64_t seed, int apw, int vec,
                                                        int32_t *__restrict__ out) {
-    constexpr int PW = 64 / B;
+    static_assert(B == 16 || B == 64, "lanes per permutation");
     extern __shared__ __align__(16) unsigned char smem[];
     E *arr = reinterpret_cast<E *>(smem);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int ppg = (nthr / 64) * PW;                 // permutations per work-group
+    const int ppg = (nthr / 64) * apw;                // permutations per work-group (apw per wave)
     const int64_t p0 = (int64_t)blockIdx.x * ppg;
     int live = ppg;
     if (p0 + live > P) live = (int)(P - p0);
@@ -134,8 +141,8 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
 
     const int wave = tid / 64, lane = tid % 64;
     const int ps = lane / B, t = lane % B;          // permutation slot in the wave, lane in group
-    const int slot = wave * PW + ps;
-    const bool mine = slot < live;
+    const int slot = wave * apw + ps;
+    const bool mine = ps < apw && slot < live;
     const int gbase = (lane / B) * B;               // first lane of the group
     E *a = arr + (int64_t)(mine ? slot : 0) * n;
     const uint64_t start = stream_start(seed, (uint64_t)(p0 + slot));
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         const int64_t j = (int64_t)(m >> 32);
         bool ok = true;
         if (valid && lo < sb) ok = lo >= (uint32_t)(0u - sb) % sb;
-        const uint64_t gmask = (B == 64) ? ~0ull : (((1ull << B) - 1) << gbase);
+        const uint64_t gmask = group_mask<B>(gbase);
         // A rejected draw shifts every later step of the batch onto another
         // draw: such a group replays the batch in order (rare).
         const bool grej = (__ballot(valid && !ok) & gmask) != 0;
@@ -168,15 +175,26 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         if (lowtop < 1) lowtop = 1;
         bool conflict = real && j >= lowtop && j < it;
         // Every other lane's partner key (idle lanes and self-swaps carry ~t,
-        // which no partner or top index equals): two equal partners, or a
-        // partner on this lane's top index.
+        // which no partner, top index or other key equals): two equal
+        // partners, or a partner on this lane's top index.  A zero of
+        // key ^ other or it ^ other marks it; the minimum over the group is
+        // kept with one three-operand min per lane rotated in.
         const uint32_t key = real ? (uint32_t)j : ~(uint32_t)t;
+        const uint32_t itu = (uint32_t)it;
+        uint32_t mn = 0xFFFFFFFFu;
+        uint32_t kr = key;
 #pragma unroll
         for (int r = 1; r < B; r++) {
-            const uint32_t ko = rotate_in_group<B>(key, r, gbase, t);
-            if ((real && ko == key) || ko == (uint32_t)it) conflict = true;
+            uint32_t ko;
+            if constexpr (B == 16) {
+                ko = rotate_row(key, r);
+            } else {
+                kr = rotate_wave1(kr);      // B == 64: every lane in turn
+                ko = kr;
+            }
+            mn = min(min(mn, ko ^ key), ko ^ itu);
         }
-        conflict = conflict && valid;
+        conflict = (conflict || mn == 0) && valid;
 
         // swaps without conflict, all at once; the next batch's draw is
         // computed while they are in flight
@@ -315,24 +333,32 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
     return 0;
 }
 
-// Batched form: up to four waves per work-group (one per SIMD) sharing the
-// arrays that fit; each wave takes PW = 64 / B of them, PW the largest power
-// of two with four waves' worth of arrays (at most 8, at least 1).
+// Batched form: up to four waves per work-group (one per SIMD), up to 16
+// arrays; B = 16 lanes per permutation and 1, 2 or 4 arrays per wave when at
+// least four arrays fit, else B = 64 and one array per wave.
 template <typename E>
 int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t *out,
                  size_t lds_limit, hipStream_t s) {
     const size_t row = (size_t)n * sizeof(E);
     const size_t spare = 256 * sizeof(E);        // the per-thread dummy slots
     if (lds_limit <= spare) return 1;
-    const int64_t fit = (int64_t)((lds_limit - spare) / row);
+    int64_t fit = (int64_t)((lds_limit - spare) / row);
     if (fit < 1) return 1;
-    int pw = 1;
-    while (pw < 8 && 2 * pw * 4 <= fit) pw *= 2;
-    const int B = 64 / pw;
-    int64_t waves = fit / pw;
-    if (waves > 4) waves = 4;
-    // no more waves than the permutations need
-    while (waves > 1 && (waves - 1) * pw >= P) --waves;
+    if (fit > 16) fit = 16;
+    if (fit > P) fit = P;
+    int B, pw;
+    int64_t waves;
+    if (fit >= 4) {
+        B = 16;
+        pw = (int)ceil_div(fit, 4);
+        if (pw == 3) pw = 2;                     // 1, 2 or 4 arrays per wave
+        waves = fit / pw;
+        if (waves > 4) waves = 4;
+    } else {
+        B = 64;
+        pw = 1;
+        waves = fit;
+    }
     const int64_t ppg = waves * pw;
     const size_t bytes = (size_t)ppg * row + spare;
     const int64_t blocks = ceil_div(P, ppg);
@@ -342,13 +368,11 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32
     if (B == B_) {                                                                               \
         (void)hipFuncSetAttribute((const void *)k_permute_batch<E, B_>,                          \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);       \
-        hipLaunchKernelGGL((k_permute_batch<E, B_>), grid, block, bytes, s, base, n, P, seed, vec, \
-                           out);                                                                 \
+        hipLaunchKernelGGL((k_permute_batch<E, B_>), grid, block, bytes, s, base, n, P, seed, pw, \
+                           vec, out);                                                            \
         return 0;                                                                                \
     }
-    PSTAT_BATCH_CASE(8)
     PSTAT_BATCH_CASE(16)
-    PSTAT_BATCH_CASE(32)
     PSTAT_BATCH_CASE(64)
 #undef PSTAT_BATCH_CASE
     return 1;
