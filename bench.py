@@ -310,8 +310,12 @@ def main() -> int:
     else:
         work = PLAIN_OPS_PER_PAIRPERM * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12
+        traffic = None
+        if args.config == 1:
+            traffic = recorded_traffic("paper_2505_04556_amd/csrc/k_plain.hip",
+                                       "profiles/k_plain_f32_n10000_hbm_traffic.txt")
         roof = dict(bound="alu", achieved=round(achieved, 2), peak=round(PEAK_VALU_TOPS, 2),
-                    unit="TFLOP/s", frac=round(achieved / PEAK_VALU_TOPS, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_VALU_TOPS, 4), traffic=traffic,
                     kernel="k_plain<32,256,float>", kernel_ms=round(kern_ms, 4),
                     work_per_launch=f"{PLAIN_OPS_PER_PAIRPERM} VALU lane-ops x {pairs} pairs x "
                                     f"{R} groupings")
@@ -341,6 +345,18 @@ def main() -> int:
                       "max_rel_err_vs_oracle_sample": acc.get(p)}
                   for p, v in runs.items()},
     }
+    # HBM side of the plain kernel (VALU-bound): recorded counter traffic over
+    # this run's kernel time
+    if "plain_f32" in runs and args.config == 1:
+        t = recorded_traffic("paper_2505_04556_amd/csrc/k_plain.hip",
+                             "profiles/k_plain_f32_n10000_hbm_traffic.txt")
+        v = runs["plain_f32"]
+        kms = v["kernel_ms_total"] / max(1, v["kernel_launches"])
+        if t is not None:
+            out["paths"]["plain_f32"]["hbm"] = dict(
+                traffic_bytes=t, GB_per_s=round(t / (kms / 1e3) / 1e9, 1),
+                frac_of_8TBps=round(t / (kms / 1e3) / 8e12, 4),
+                passes_over_matrix=-(-R // 256))
     if speedup is not None:
         out["speedup_n25000"] = speedup
     if serve is not None:
