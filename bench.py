@@ -149,6 +149,32 @@ def cpu_baseline(D_host, cfg, target_s=12.0):
                 perms_array=perms)
 
 
+def gemm_ceiling(torch, shapes=((16384, 16384, 16384), (10000, 50000, 10000)), reps=5):
+    """The vendor library's dense BF16 rate on this GPU (torch.matmul, which
+    runs hipBLASLt): what a plain GEMM reaches here under the chip's power and
+    clock limits, beside the nominal 2.5 PFLOP/s peak."""
+    res = {}
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for (m, nn, kk) in shapes:
+        a = torch.randn(m, kk, device="cuda", dtype=torch.bfloat16, generator=g)
+        b = torch.randn(kk, nn, device="cuda", dtype=torch.bfloat16, generator=g)
+        for _ in range(2):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{m}x{nn}x{kk}"] = {"ms": round(ms, 4),
+                                 "TFLOP_per_s": round(2.0 * m * nn * kk / (ms * 1e-3) / 1e12, 1)}
+        del a, b, c
+    torch.cuda.empty_cache()
+    return res
+
+
 def recorded_traffic(kernel_src: str, summary: str):
     """HBM bytes per launch from a committed counter summary, or None when the
     kernel source has changed since the counters were taken."""
@@ -209,6 +235,10 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuning")
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the n=25,000 plain-vs-split-BF16 comparison")
+    ap.add_argument("--no-gemm", action="store_true",
+                    help="skip the vendor BF16 GEMM rate measured for context")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="measure only the vendor BF16 GEMM rate (for profiling it)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -234,6 +264,9 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.gemm_only:
+        print(json.dumps({"gemm_bf16_torch_matmul": gemm_ceiling(torch)}), flush=True)
+        return 0
     cfg = synth.config(args.config)
     n, k, P = cfg["n"], cfg["k"], cfg["n_perms"]
     log(f"workload {cfg['name']}: generating the matrix on the device")
@@ -271,6 +304,12 @@ def main() -> int:
         log("speedup leg: n=25,000, k=10, 3,999 permutations, plain FP32 vs split BF16")
         speedup = speedup_leg(ps, torch, sd, synth)
         log(f"  {speedup}")
+
+    gemm = None
+    if not args.no_gemm:
+        log("vendor BF16 GEMM rate (torch.matmul) for context")
+        gemm = gemm_ceiling(torch)
+        log(f"  {gemm}")
 
     serve = None
     if not args.no_serve:
@@ -357,6 +396,13 @@ def main() -> int:
                 traffic_bytes=t, GB_per_s=round(t / (kms / 1e3) / 1e9, 1),
                 frac_of_8TBps=round(t / (kms / 1e3) / 8e12, 4),
                 passes_over_matrix=-(-R // 256))
+    if gemm is not None:
+        best_gemm = max(v["TFLOP_per_s"] for v in gemm.values())
+        out["mfma_context"] = {
+            "vendor_bf16_gemm": gemm,
+            "note": "torch.matmul (hipBLASLt) dense BF16 on this GPU, same power limits",
+            "roofline_achieved_over_best_gemm": (round(roof["achieved"] / best_gemm, 4)
+                                                 if roof["bound"] == "mfma" else None)}
     if speedup is not None:
         out["speedup_n25000"] = speedup
     if serve is not None:

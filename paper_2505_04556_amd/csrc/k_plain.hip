@@ -206,13 +206,18 @@ void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t
 // pairs (one column, every fourth row), holds their d^2 in FP64 registers, and
 // for each of EQ groupings adds the d^2 of its pairs whose two labels agree,
 // times that label's weight (Algorithm 1's sum, split by column).  D is read
-// once for all EQ groupings.  A work-group walks a contiguous run of tiles and
-// writes one partial per grouping; every sum has a fixed order (wave
-// shuffles, then per-wave running sums, then the four waves in order, then the
-// runs in order), so results are reproducible.
+// once for all EQ groupings.  A pair counts through an FMA with an exact 0 or
+// 1 factor (compare, select of the factor's upper word, FMA), and each thread
+// keeps one running FP64 sum per grouping over the whole run of tiles; the
+// cross-lane sums happen once per work-group.  The D entries and labels of
+// the next tile are loaded while the current one is computed.  Every sum has
+// a fixed order (rows within a tile, tiles of the run, a butterfly over the
+// wave, the four waves in order, then the runs in order), so results are
+// reproducible.
 constexpr int kFT = 64;               // tile edge
 constexpr int64_t kFewChunks = 4096;  // work-groups (tile runs) per launch
 constexpr int64_t kFewMaxM = 1024;    // groupings per launch
+constexpr int kFewWLds = 1024;        // weights kept in LDS up to this many groups
 
 template <int EQ>
 __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, int64_t n,
@@ -221,46 +226,99 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
                                                 const int32_t *__restrict__ rows, int64_t m,
                                                 int32_t k, const double *__restrict__ w,
                                                 double *__restrict__ partial, int64_t m_pad) {
-    __shared__ int32_t sl[EQ][2][kFT];      // [grouping][rows, columns][64]
+    static_assert(EQ % 2 == 0, "two groupings per label round");
+    constexpr int LR = EQ / 2;   // label loads per thread and tile
+    // row labels as [grouping][row % 4][row / 4], so the 16 rows of a thread
+    // (wave + 4u) are four 16-byte reads; column labels and their weights
+    __shared__ __align__(16) int32_t srow[EQ][4][16];
+    __shared__ int32_t scol[EQ][kFT];
+    __shared__ double swc[EQ][kFT];
     __shared__ double sred[4][EQ];
+    __shared__ double sw[kFewWLds];
     const int tid = threadIdx.x;
     const int wave = tid / 64, c = tid % 64;
+    // label round r of this thread: grouping wave / 2 + 2r, rows (even waves)
+    // or columns (odd waves), tile position c
+    const int side = wave % 2;
     const int64_t q0 = (int64_t)blockIdx.y * EQ;
-    if (tid < 4 * EQ) sred[tid / EQ][tid % EQ] = 0.0;
-    const int64_t t_end = ((int64_t)blockIdx.x + 1) * tpc < tiles ? ((int64_t)blockIdx.x + 1) * tpc
-                                                                  : tiles;
-    for (int64_t t = (int64_t)blockIdx.x * tpc; t < t_end; t++) {
+    const bool wl = k <= kFewWLds;
+    if (wl)
+        for (int e = tid; e < k; e += 256) sw[e] = w[e];
+    int64_t gb[LR];
+#pragma unroll
+    for (int r = 0; r < LR; r++) {
+        const int64_t q = q0 + wave / 2 + 2 * r;
+        gb[r] = q < m ? (int64_t)rows[q] * n : -1;
+    }
+    double acc[EQ];
+#pragma unroll
+    for (int q = 0; q < EQ; q++) acc[q] = 0.0;
+    const int64_t t0 = (int64_t)blockIdx.x * tpc;
+    const int64_t t_end = t0 + tpc < tiles ? t0 + tpc : tiles;
+
+    float dn[16];        // D entries of the next tile (0 off the strict triangle)
+    int32_t ln[LR];      // labels of the next tile (padding never matches)
+    auto fetch = [&](int64_t t) {
         int64_t I, J;
         tri_decode(t, nt, I, J);
-        __syncthreads();   // the previous tile's labels are no longer read
-        // labels of this tile's rows and columns; padding never matches a column
-        for (int e = tid; e < EQ * 2 * kFT; e += 256) {
-            const int q = e / (2 * kFT), side = (e / kFT) % 2, x = e % kFT;
-            const int64_t idx = (side ? J : I) * kFT + x;
-            int32_t v = -1 - side;
-            if (q0 + q < m && idx < n) v = g[(int64_t)rows[q0 + q] * n + idx];
-            sl[q][side][x] = v;
-        }
         const int64_t j = J * kFT + c;
-        double d2[16];
 #pragma unroll
         for (int u = 0; u < 16; u++) {
             const int64_t i = I * kFT + wave + 4 * u;
-            d2[u] = (j < n && i < j) ? square<double>(mat[i * n + j]) : 0.0;
+            dn[u] = (j < n && i < j) ? mat[i * n + j] : 0.0f;
+        }
+        const int64_t idx = (side ? J : I) * kFT + c;
+#pragma unroll
+        for (int r = 0; r < LR; r++) ln[r] = (gb[r] >= 0 && idx < n) ? g[gb[r] + idx] : -1 - side;
+    };
+    if (t0 < t_end) fetch(t0);
+    __syncthreads();   // weights in LDS
+    for (int64_t t = t0; t < t_end; t++) {
+        double d2[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) d2[u] = (double)dn[u] * (double)dn[u];
+#pragma unroll
+        for (int r = 0; r < LR; r++) {
+            const int q = wave / 2 + 2 * r;
+            const int32_t v = ln[r];
+            if (side) {
+                scol[q][c] = v;
+                swc[q][c] = (v >= 0 && v < k) ? (wl ? sw[v] : w[v]) : 0.0;
+            } else {
+                srow[q][c % 4][c / 4] = v;
+            }
         }
         __syncthreads();
-#pragma unroll 2
+        if (t + 1 < t_end) fetch(t + 1);
+#pragma unroll
         for (int q = 0; q < EQ; q++) {
-            const int32_t lc = sl[q][1][c];
-            const double wc = (lc >= 0 && lc < k) ? w[lc] : 0.0;
+            const int32_t lc = scol[q][c];
+            const int4 *rl = reinterpret_cast<const int4 *>(&srow[q][wave][0]);
+            int32_t li[16];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int4 r4 = rl[v];
+                li[4 * v] = r4.x;
+                li[4 * v + 1] = r4.y;
+                li[4 * v + 2] = r4.z;
+                li[4 * v + 3] = r4.w;
+            }
             double sum = 0.0;
 #pragma unroll
-            for (int u = 0; u < 16; u++) sum += (sl[q][0][wave + 4 * u] == lc) ? d2[u] : 0.0;
-            double v = sum * wc;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-            if (c == 0) sred[wave][q] += v;
+            for (int u = 0; u < 16; u++) {
+                const int hi = li[u] == lc ? 0x3FF00000 : 0;   // upper word of 1.0 or 0.0
+                sum = __builtin_fma(__hiloint2double(hi, 0), d2[u], sum);
+            }
+            acc[q] = __builtin_fma(sum, swc[q][c], acc[q]);
         }
+        __syncthreads();   // this tile's labels are no longer read
+    }
+#pragma unroll
+    for (int q = 0; q < EQ; q++) {
+        double v = acc[q];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (c == 0) sred[wave][q] = v;
     }
     __syncthreads();
     if (tid < EQ && q0 + tid < m)
@@ -356,7 +414,10 @@ void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t 
     for (int64_t b = 0; b < m; b += kFewMaxM) {
         const int64_t mm = m - b < kFewMaxM ? m - b : kFewMaxM;
         const int64_t m_pad = round_up(mm, 8);
-        if (mm <= 8)
+        if (mm <= 4)
+            hipLaunchKernelGGL(k_sw_few<4>, dim3((unsigned)used, 1), dim3(256), 0, s, mat, n, nt,
+                               tiles, tpc, g, rows + b, mm, k, w, partial, m_pad);
+        else if (mm <= 8)
             hipLaunchKernelGGL(k_sw_few<8>, dim3((unsigned)used, 1), dim3(256), 0, s, mat, n, nt,
                                tiles, tpc, g, rows + b, mm, k, w, partial, m_pad);
         else
