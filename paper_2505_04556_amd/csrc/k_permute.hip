@@ -150,8 +150,10 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
     // one private LDS slot per thread after the arrays: the target of the
     // swap of a lane with nothing to swap, so the swap needs no branch
     E *const dummy = arr + (int64_t)ppg * n + tid;
-    uint32_t x = (uint32_t)(mix64(start + ((uint64_t)t + 1) * kGamma) >> 32);
-    for (uint64_t d = 0;; d += B) {
+    // this lane's counter, start + (d + t + 1) * gamma, advanced by B draws per batch
+    uint64_t ctr = start + ((uint64_t)t + 1) * kGamma;
+    uint32_t x = (uint32_t)(mix64(ctr) >> 32);
+    for (;;) {
         // the wave runs until all of its permutations are done
         if (__ballot(top >= 1) == 0) break;
         const int64_t it = top - t;                  // this lane's step if nothing is rejected
@@ -173,16 +175,17 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         const bool real = valid && j != it;
         int64_t lowtop = top - B + 1;
         if (lowtop < 1) lowtop = 1;
+        // a partner on a later step's top index (top - s for some s > t)
         bool conflict = real && j >= lowtop && j < it;
-        // Every other lane's partner key (idle lanes and self-swaps carry ~t,
-        // which no partner, top index or other key equals): two equal
-        // partners, or a partner on this lane's top index.  A zero of
-        // key ^ other or it ^ other marks it; the minimum over the group is
-        // kept with one three-operand min per lane rotated in.
+        // Two equal partners: every other lane's partner key (idle lanes and
+        // self-swaps carry ~t, which no partner or other key equals) is
+        // compared with this lane's; a zero of key ^ other marks it, and the
+        // minimum over the group is kept with one three-operand min per two
+        // lanes rotated in.
         const uint32_t key = real ? (uint32_t)j : ~(uint32_t)t;
-        const uint32_t itu = (uint32_t)it;
         uint32_t mn = 0xFFFFFFFFu;
         uint32_t kr = key;
+        uint32_t prev = 0xFFFFFFFFu;
 #pragma unroll
         for (int r = 1; r < B; r++) {
             uint32_t ko;
@@ -192,21 +195,58 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
                 kr = rotate_wave1(kr);      // B == 64: every lane in turn
                 ko = kr;
             }
-            mn = min(min(mn, ko ^ key), ko ^ itu);
+            if (r % 2 == 1) {
+                prev = ko ^ key;
+            } else {
+                mn = min(min(mn, prev), ko ^ key);
+                prev = 0xFFFFFFFFu;
+            }
         }
-        conflict = (conflict || mn == 0) && valid;
+        mn = min(mn, prev);
+        // A step whose top index is another step's partner: the partners on
+        // top indices set bit s (top - j) of a group-wide mask.
+        uint32_t hit;
+        if constexpr (B == 16) {
+            // OR over the 16 lanes of the row: rotations by 8, 4, 2, 1
+            uint32_t hm = conflict ? 1u << (uint32_t)(top - j) : 0u;
+            hm |= rotate_row(hm, 8);
+            hm |= rotate_row(hm, 4);
+            hm |= rotate_row(hm, 2);
+            hm |= rotate_row(hm, 1);
+            hit = (hm >> t) & 1u;
+        } else {
+            // B == 64: a 64-bit mask, OR-reduced over the wave by a butterfly
+            uint32_t lo = 0, hi = 0;
+            if (conflict) {
+                const uint32_t s = (uint32_t)(top - j);
+                lo = s < 32 ? 1u << s : 0u;
+                hi = s < 32 ? 0u : 1u << (s - 32);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                lo |= (uint32_t)__shfl_xor((int)lo, off);
+                hi |= (uint32_t)__shfl_xor((int)hi, off);
+            }
+            hit = ((t < 32 ? lo >> t : hi >> (t - 32))) & 1u;
+        }
+        conflict = (conflict || mn == 0 || hit != 0) && valid;
 
         // swaps without conflict, all at once; the next batch's draw is
-        // computed while they are in flight
+        // computed while their reads are in flight (a scheduling barrier
+        // keeps it after the reads, the empty asm before the writes)
+        uint32_t xn;
         {
             const bool now = valid && !conflict && mine && !grej;
             E *pa = now ? a + it : dummy;
             E *pb = now ? a + j : dummy;
             const E va = *pa, vb = *pb;
+            __builtin_amdgcn_sched_barrier(0);
+            ctr += (uint64_t)B * kGamma;
+            xn = (uint32_t)(mix64(ctr) >> 32);
+            asm volatile("" : "+v"(xn));
             *pa = vb;
             *pb = va;
         }
-        const uint32_t xn = (uint32_t)(mix64(start + (d + B + (uint64_t)t + 1) * kGamma) >> 32);
 
         if (__ballot(grej) != 0) {
             // gather the group's draws into its first lane, all lanes active
