@@ -106,37 +106,159 @@ __device__ inline uint64_t group_mask(int gbase) {
     else return ((1ull << B) - 1) << gbase;
 }
 
+// Label storage of the batched shuffle.  WideStore keeps one label per
+// 8- or 16-bit entry; each lane with nothing to swap swaps a private dummy
+// slot, so a batch's writes never race.  NibbleStore packs labels below 16
+// eight to a 32-bit word (n = 10,000 takes 5,000 bytes, so twice as many
+// arrays share a CU's LDS) and writes by xor: a swap of values u and v adds
+// u ^ v into both positions with an LDS atomic xor, so swaps of different
+// positions in one word commute, and a lane with nothing to swap adds zero.
+template <typename E>
+struct WideStore {
+    static constexpr size_t row_bytes(int64_t n) { return (size_t)n * sizeof(E); }
+    static constexpr size_t spare_bytes() { return 256 * sizeof(E); }
+    E *a;        // this lane's array
+    E *dummy;    // this thread's private slot
+    __device__ WideStore(unsigned char *smem, int64_t n, int slot, int ppg, int tid)
+        : a(reinterpret_cast<E *>(smem) + (int64_t)slot * n),
+          dummy(reinterpret_cast<E *>(smem) + (int64_t)ppg * n + tid) {}
+    __device__ void swap(int64_t i, int64_t j) const {
+        const E ai = a[i], aj = a[j];
+        a[i] = aj;
+        a[j] = ai;
+    }
+    // the batch's parallel swap; `between` runs after the reads are issued
+    template <typename F>
+    __device__ void swap_all(bool now, int64_t i, int64_t j, F &&between) const {
+        E *pa = now ? a + i : dummy;
+        E *pb = now ? a + j : dummy;
+        const E va = *pa, vb = *pb;
+        between();
+        *pa = vb;
+        *pb = va;
+    }
+    // Copy in: each base label is loaded once (four per load when `vec`) and
+    // written into every live array.
+    __device__ static void fill(unsigned char *smem, const int32_t *base, int64_t n, int live,
+                                int vec, int tid, int nthr) {
+        E *arr = reinterpret_cast<E *>(smem);
+        const int64_t n4 = vec ? n / 4 : 0;
+        const int4 *base4 = reinterpret_cast<const int4 *>(base);
+        for (int64_t v = tid; v < n4; v += nthr) {
+            const int4 b = base4[v];
+            for (int q = 0; q < live; q++) {
+                E *d = arr + (int64_t)q * n + 4 * v;
+                d[0] = (E)b.x;
+                d[1] = (E)b.y;
+                d[2] = (E)b.z;
+                d[3] = (E)b.w;
+            }
+        }
+        for (int64_t i = 4 * n4 + tid; i < n; i += nthr) {
+            const E b = (E)base[i];
+            for (int q = 0; q < live; q++) arr[(int64_t)q * n + i] = b;
+        }
+    }
+    // Copy out, 16-byte stores when `vec`.
+    __device__ static void drain(const unsigned char *smem, int32_t *out, int64_t p0, int64_t n,
+                                 int live, int vec, int tid, int nthr) {
+        const E *arr = reinterpret_cast<const E *>(smem);
+        const int64_t n4 = vec ? n / 4 : 0;
+        for (int q = 0; q < live; q++) {
+            const E *src = arr + (int64_t)q * n;
+            int32_t *dst = out + (p0 + q) * n;
+            int4 *dst4 = reinterpret_cast<int4 *>(dst);
+            for (int64_t v = tid; v < n4; v += nthr)
+                dst4[v] = make_int4(src[4 * v], src[4 * v + 1], src[4 * v + 2], src[4 * v + 3]);
+            for (int64_t i = 4 * n4 + tid; i < n; i += nthr) dst[i] = (int32_t)src[i];
+        }
+    }
+};
+
+struct NibbleStore {
+    static constexpr size_t row_bytes(int64_t n) { return (size_t)((n + 7) / 8) * 4; }
+    static constexpr size_t spare_bytes() { return 0; }
+    uint32_t *w;   // this lane's array, eight labels per word
+    __device__ NibbleStore(unsigned char *smem, int64_t n, int slot, int, int)
+        : w(reinterpret_cast<uint32_t *>(smem) + (int64_t)slot * ((n + 7) / 8)) {}
+    __device__ uint32_t get(int64_t i) const { return (w[i >> 3] >> (4 * (uint32_t)(i & 7))) & 15u; }
+    __device__ void flip(int64_t i, uint32_t d) const {
+        atomicXor(&w[i >> 3], d << (4 * (uint32_t)(i & 7)));
+    }
+    __device__ void swap(int64_t i, int64_t j) const {
+        const uint32_t d = get(i) ^ get(j);
+        flip(i, d);
+        flip(j, d);
+    }
+    template <typename F>
+    __device__ void swap_all(bool now, int64_t i, int64_t j, F &&between) const {
+        const int64_t ia = now ? i : 0, ib = now ? j : 0;
+        const uint32_t wa = w[ia >> 3], wb = w[ib >> 3];
+        between();
+        const uint32_t sa = 4 * (uint32_t)(ia & 7), sb = 4 * (uint32_t)(ib & 7);
+        const uint32_t d = ((wa >> sa) ^ (wb >> sb)) & 15u;   // 0 for a lane with nothing to swap
+        atomicXor(&w[ia >> 3], d << sa);
+        atomicXor(&w[ib >> 3], d << sb);
+    }
+    __device__ static void fill(unsigned char *smem, const int32_t *base, int64_t n, int live,
+                                int vec, int tid, int nthr) {
+        uint32_t *arr = reinterpret_cast<uint32_t *>(smem);
+        const int64_t nw = (n + 7) / 8;
+        for (int64_t v = tid; v < nw; v += nthr) {
+            uint32_t word = 0;
+            if (vec && 8 * v + 8 <= n) {
+                const int4 b0 = reinterpret_cast<const int4 *>(base)[2 * v];
+                const int4 b1 = reinterpret_cast<const int4 *>(base)[2 * v + 1];
+                word = (uint32_t)b0.x | (uint32_t)b0.y << 4 | (uint32_t)b0.z << 8 |
+                       (uint32_t)b0.w << 12 | (uint32_t)b1.x << 16 | (uint32_t)b1.y << 20 |
+                       (uint32_t)b1.z << 24 | (uint32_t)b1.w << 28;
+            } else {
+                for (int e = 0; e < 8; e++)
+                    if (8 * v + e < n) word |= (uint32_t)base[8 * v + e] << (4 * e);
+            }
+            for (int q = 0; q < live; q++) arr[(int64_t)q * nw + v] = word;
+        }
+    }
+    __device__ static void drain(const unsigned char *smem, int32_t *out, int64_t p0, int64_t n,
+                                 int live, int vec, int tid, int nthr) {
+        const uint32_t *arr = reinterpret_cast<const uint32_t *>(smem);
+        const int64_t nw = (n + 7) / 8;
+        for (int q = 0; q < live; q++) {
+            const uint32_t *src = arr + (int64_t)q * nw;
+            int32_t *dst = out + (p0 + q) * n;
+            for (int64_t v = tid; v < nw; v += nthr) {
+                const uint32_t word = src[v];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int64_t i0 = 8 * v + 4 * h;
+                    const uint32_t x = word >> (16 * h);
+                    if (vec && i0 + 4 <= n) {
+                        *reinterpret_cast<int4 *>(dst + i0) =
+                            make_int4(x & 15u, (x >> 4) & 15u, (x >> 8) & 15u, (x >> 12) & 15u);
+                    } else {
+                        for (int e = 0; e < 4; e++)
+                            if (i0 + e < n) dst[i0 + e] = (int32_t)((x >> (4 * e)) & 15u);
+                    }
+                }
+            }
+        }
+    }
+};
+
 // Batched shuffle: B lanes per permutation, 64 / B permutations per wave,
-// blockDim.x / 64 waves per work-group, arrays in dynamic LDS.
-template <typename E, int B>
+// blockDim.x / 64 waves per work-group, arrays in dynamic LDS as S stores them.
+template <typename S, int B>
 __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict__ base, int64_t n,
                                                        int64_t P, uint64_t seed, int apw, int vec,
                                                        int32_t *__restrict__ out) {
     static_assert(B == 16 || B == 64, "lanes per permutation");
     extern __shared__ __align__(16) unsigned char smem[];
-    E *arr = reinterpret_cast<E *>(smem);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ppg = (nthr / 64) * apw;                // permutations per work-group (apw per wave)
     const int64_t p0 = (int64_t)blockIdx.x * ppg;
     int live = ppg;
     if (p0 + live > P) live = (int)(P - p0);
-    // copy in (as in the one-lane form)
-    const int64_t n4 = vec ? n / 4 : 0;
-    const int4 *base4 = reinterpret_cast<const int4 *>(base);
-    for (int64_t v = tid; v < n4; v += nthr) {
-        const int4 b = base4[v];
-        for (int q = 0; q < live; q++) {
-            E *d = arr + (int64_t)q * n + 4 * v;
-            d[0] = (E)b.x;
-            d[1] = (E)b.y;
-            d[2] = (E)b.z;
-            d[3] = (E)b.w;
-        }
-    }
-    for (int64_t i = 4 * n4 + tid; i < n; i += nthr) {
-        const E b = (E)base[i];
-        for (int q = 0; q < live; q++) arr[(int64_t)q * n + i] = b;
-    }
+    S::fill(smem, base, n, live, vec, tid, nthr);
     __syncthreads();
 
     const int wave = tid / 64, lane = tid % 64;
@@ -144,12 +266,9 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
     const int slot = wave * apw + ps;
     const bool mine = ps < apw && slot < live;
     const int gbase = (lane / B) * B;               // first lane of the group
-    E *a = arr + (int64_t)(mine ? slot : 0) * n;
+    const S a(smem, n, mine ? slot : 0, ppg, tid);
     const uint64_t start = stream_start(seed, (uint64_t)(p0 + slot));
     int64_t top = mine ? n - 1 : 0;                 // current i of the permutation
-    // one private LDS slot per thread after the arrays: the target of the
-    // swap of a lane with nothing to swap, so the swap needs no branch
-    E *const dummy = arr + (int64_t)ppg * n + tid;
     // this lane's counter, start + (d + t + 1) * gamma, advanced by B draws per batch
     uint64_t ctr = start + ((uint64_t)t + 1) * kGamma;
     uint32_t x = (uint32_t)(mix64(ctr) >> 32);
@@ -235,18 +354,12 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         // computed while their reads are in flight (a scheduling barrier
         // keeps it after the reads, the empty asm before the writes)
         uint32_t xn;
-        {
-            const bool now = valid && !conflict && mine && !grej;
-            E *pa = now ? a + it : dummy;
-            E *pb = now ? a + j : dummy;
-            const E va = *pa, vb = *pb;
+        a.swap_all(valid && !conflict && mine && !grej, it, j, [&]() {
             __builtin_amdgcn_sched_barrier(0);
             ctr += (uint64_t)B * kGamma;
             xn = (uint32_t)(mix64(ctr) >> 32);
             asm volatile("" : "+v"(xn));
-            *pa = vb;
-            *pb = va;
-        }
+        });
 
         if (__ballot(grej) != 0) {
             // gather the group's draws into its first lane, all lanes active
@@ -263,10 +376,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
                         const uint32_t lr = (uint32_t)mr;
                         // a rejected draw is consumed and the step keeps its bound
                         if (!(lr < sr && lr < (uint32_t)(0u - sr) % sr)) {
-                            const int64_t jr = (int64_t)(mr >> 32);
-                            const E ai = a[i], aj = a[jr];
-                            a[i] = aj;
-                            a[jr] = ai;
+                            a.swap(i, (int64_t)(mr >> 32));
                             --i;
                         }
                     }
@@ -280,26 +390,14 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         while (cm != 0) {
             const uint64_t g = cm & gmask;
             const bool turn = g != 0 && lane == __builtin_ctzll(g);
-            if (turn) {
-                const E ai = a[it], aj = a[j];
-                a[it] = aj;
-                a[j] = ai;
-            }
+            if (turn) a.swap(it, j);
             cm &= ~__ballot(turn);
         }
         if (!grej) top = top - B < 0 ? 0 : top - B;
         x = xn;
     }
     __syncthreads();
-    // copy out
-    for (int q = 0; q < live; q++) {
-        const E *src = arr + (int64_t)q * n;
-        int32_t *dst = out + (p0 + q) * n;
-        int4 *dst4 = reinterpret_cast<int4 *>(dst);
-        for (int64_t v = tid; v < n4; v += nthr)
-            dst4[v] = make_int4(src[4 * v], src[4 * v + 1], src[4 * v + 2], src[4 * v + 3]);
-        for (int64_t i = 4 * n4 + tid; i < n; i += nthr) dst[i] = (int32_t)src[i];
-    }
+    S::drain(smem, out, p0, n, live, vec, tid, nthr);
 }
 
 template <typename E>
@@ -375,12 +473,13 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
 
 // Batched form: up to four waves per work-group (one per SIMD), up to 16
 // arrays; B = 16 lanes per permutation and 1, 2 or 4 arrays per wave when at
-// least four arrays fit, else B = 64 and one array per wave.
-template <typename E>
+// least four arrays fit, else B = 64 and one array per wave.  Work-groups
+// small enough share a CU.
+template <typename S>
 int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t *out,
                  size_t lds_limit, hipStream_t s) {
-    const size_t row = (size_t)n * sizeof(E);
-    const size_t spare = 256 * sizeof(E);        // the per-thread dummy slots
+    const size_t row = S::row_bytes(n);
+    const size_t spare = S::spare_bytes();       // the per-thread dummy slots
     if (lds_limit <= spare) return 1;
     int64_t fit = (int64_t)((lds_limit - spare) / row);
     if (fit < 1) return 1;
@@ -406,9 +505,9 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32
     const dim3 grid((unsigned)blocks), block((unsigned)(64 * waves));
 #define PSTAT_BATCH_CASE(B_)                                                                     \
     if (B == B_) {                                                                               \
-        (void)hipFuncSetAttribute((const void *)k_permute_batch<E, B_>,                          \
+        (void)hipFuncSetAttribute((const void *)k_permute_batch<S, B_>,                          \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);       \
-        hipLaunchKernelGGL((k_permute_batch<E, B_>), grid, block, bytes, s, base, n, P, seed, pw, \
+        hipLaunchKernelGGL((k_permute_batch<S, B_>), grid, block, bytes, s, base, n, P, seed, pw, \
                            vec, out);                                                            \
         return 0;                                                                                \
     }
@@ -423,8 +522,12 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
                    int32_t *out, size_t lds_limit, hipStream_t s) {
     if (P <= 0 || n <= 0) return 0;
-    if (max_label < 256 && launch_batch<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
-    if (max_label < 65536 && launch_batch<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)
+    if (max_label < 16 && launch_batch<NibbleStore>(base, n, P, seed, out, lds_limit, s) == 0)
+        return 0;
+    if (max_label < 256 && launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, lds_limit, s) == 0)
+        return 0;
+    if (max_label < 65536 &&
+        launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, lds_limit, s) == 0)
         return 0;
     if (max_label < 256 && launch_lds<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
     if (max_label < 65536 && launch_lds<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)

@@ -52,10 +52,12 @@ def test_device_generators_match_host(ps):
     (16, 2, 4, 3000), (2, 1, 7, 1), (1000, 3, 999, 3000), (500, 300, 64, 77),
     (90_000, 299, 3, 5),          # u16 labels that do not fit in LDS: in-place path
     (20_000, 4, 130, 9),          # u8 labels, several permutations per work-group
-    # batched shuffle with 16, 32 and 64 lanes per permutation; each of these
+    # batched shuffle with 16 and 64 lanes per permutation, labels packed four
+    # bits to an entry (below 16) or one byte (below 256); each of these
     # inputs has draws that Lemire's method rejects (asserted below), so the
     # in-order replay of a batch is exercised
     (10_000, 4, 400, 13), (12_000, 4, 200, 13), (60_000, 6, 24, 13),
+    (10_000, 40, 400, 13), (60_000, 100, 24, 13), (10_003, 15, 256, 13),
 ])
 def test_permute_bit_exact(ps, n, maxlab, P, seed):
     import torch
