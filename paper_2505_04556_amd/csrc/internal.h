@@ -42,6 +42,8 @@ void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_
 // then a fixed-order final sum divided by n.
 int64_t sT_partials_count(int64_t n);
 void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s);
+// s_T = (sum of count partials, fixed order) / n
+void launch_sT_final(const double *partials, int64_t count, int64_t n, double *sT, hipStream_t s);
 
 // ---- plain kernel (k_plain.hip) -------------------------------------------
 struct PlainPlan {
@@ -111,7 +113,10 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
                    int n_cu);
 size_t mfma_tile_bytes(int64_t n, int dtype);
 // Pre-pass: strict-upper d^2 of 128-row panels into MFMA fragment order.
-void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s);
+// Pre-squares the strict upper triangle into MFMA fragment order; with
+// sT_part (sT_partials_count(n) doubles) set it also leaves s_T in *sT.
+void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
+                         double *sT_part = nullptr, double *sT = nullptr);
 size_t mfma_table_bytes(const MfmaPlan &pl);
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);
 // z[item][P][k] FP32 sums of the (G^T U G) diagonal per (panel, K chunk) item;

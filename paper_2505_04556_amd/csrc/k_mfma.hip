@@ -60,54 +60,103 @@ __device__ inline uint16_t to_f16_bits(float x) {
 }
 
 // ---- pre-pass --------------------------------------------------------------
-// Block (kb, I): unit (I, kb) for kb >= 2I.  Stages the 128 x 64 FP32 block in
-// LDS (coalesced row reads), then writes 1024 uint4 per component in fragment
-// order: uint4 index ((rb * 4 + s) * 64 + lane) holds row rb*32 + lane%32,
-// columns 32*(lane/32) + 8*s + 0..7 of the block.
+// Unit (I, kb), kb >= 2I: the 128 x 64 block of rows 128I.., columns 64kb..
+// of the strict upper triangle.  A work-group walks units blockIdx.x,
+// blockIdx.x + gridDim.x, ...: it loads the FP32 block (16-byte row reads when
+// every row is 16-byte aligned), squares it into LDS, then writes 1024 uint4
+// per component in fragment order: uint4 index ((rb * 4 + s) * 64 + lane)
+// holds row rb*32 + lane%32, columns 32*(lane/32) + 8*s + 0..7 of the block.
+// With sT_part set it also sums d^2 in FP64 over the same strict upper
+// triangle (the s_T numerator) and writes one partial per work-group: threads
+// in unit order, then a butterfly over each wave, then the four waves in order.
+__device__ inline int64_t unit_panel(int64_t unit, int64_t kb_total) {
+    // first unit of panel I: I * (kb_total - I + 1)
+    const double b = (double)(kb_total + 1);
+    int64_t I = (int64_t)((b - sqrt(b * b - 4.0 * (double)unit)) * 0.5);
+    if (I < 0) I = 0;
+    while (I > 0 && I * (kb_total - I + 1) > unit) --I;
+    while ((I + 1) * (kb_total - I) <= unit) ++I;
+    return I;
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, int64_t n,
-                                                 int64_t kb_total, int64_t comp_units,
-                                                 uint4 *__restrict__ tiles) {
-    const int64_t kb = blockIdx.x, I = blockIdx.y;
-    if (kb < 2 * I) return;
+                                                 int64_t kb_total, int64_t comp_units, int vec,
+                                                 uint4 *__restrict__ tiles,
+                                                 double *__restrict__ sT_part) {
     __shared__ float sm[kPanel][kKBlock + 1];
+    __shared__ double sred[4];
     const int tid = threadIdx.x;
-    const int64_t r0 = I * kPanel, c0 = kb * kKBlock;
-    for (int idx = tid; idx < kPanel * kKBlock; idx += 256) {
-        const int r = idx / kKBlock, c = idx % kKBlock;
-        const int64_t i = r0 + r, j = c0 + c;
-        float x = 0.0f;
-        if (i < n && j < n && j > i) {
-            const float d = mat[(uint64_t)i * (uint64_t)n + j];
-            x = d * d;
-        }
-        sm[r][c] = x;
-    }
-    __syncthreads();
-    const int64_t unit = I * kb_total - I * (I - 1) + (kb - 2 * I);
-    for (int q = 0; q < 4; q++) {
-        const int idx = tid + 256 * q;
-        const int rb = idx / 256, s = (idx / 64) % 4, lane = idx % 64;
-        const int r = rb * 32 + (lane % 32);
-        const int cb = 32 * (lane / 32) + 8 * s;
-        uint32_t hw[4], lw[4];
-        for (int e2 = 0; e2 < 4; e2++) {
-            const float x0 = sm[r][cb + 2 * e2], x1 = sm[r][cb + 2 * e2 + 1];
-            if (DT == 1) {
-                hw[e2] = (uint32_t)to_f16_bits(x0) | ((uint32_t)to_f16_bits(x1) << 16);
+    const int cq = (tid % 16) * 4;   // four columns of the block
+    const int rq = tid / 16;         // row within each pass of 16 rows
+    double st = 0.0;
+    for (int64_t unit = blockIdx.x; unit < comp_units; unit += gridDim.x) {
+        const int64_t I = unit_panel(unit, kb_total);
+        const int64_t kb = 2 * I + (unit - I * (kb_total - I + 1));
+        const int64_t r0 = I * kPanel, c0 = kb * kKBlock;
+        float d[8][4];
+#pragma unroll
+        for (int ps = 0; ps < 8; ps++) {
+            const int64_t i = r0 + ps * 16 + rq, j0 = c0 + cq;
+            if (vec && i < n && j0 + 3 < n) {
+                const float4 v = *reinterpret_cast<const float4 *>(mat + (uint64_t)i * (uint64_t)n + j0);
+                d[ps][0] = v.x;
+                d[ps][1] = v.y;
+                d[ps][2] = v.z;
+                d[ps][3] = v.w;
             } else {
-                const uint16_t h0 = to_bf16_bits(x0), h1 = to_bf16_bits(x1);
-                hw[e2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-                if (DT == 2) {
-                    const uint16_t l0 = to_bf16_bits(x0 - bf16_bits_to_float(h0));
-                    const uint16_t l1 = to_bf16_bits(x1 - bf16_bits_to_float(h1));
-                    lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-                }
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    d[ps][e] = (i < n && j0 + e < n) ? mat[(uint64_t)i * (uint64_t)n + j0 + e] : 0.0f;
             }
         }
-        tiles[unit * kUnitU4 + idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-        if (DT == 2)
-            tiles[(comp_units + unit) * kUnitU4 + idx] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        __syncthreads();   // the previous unit's LDS reads are done
+#pragma unroll
+        for (int ps = 0; ps < 8; ps++) {
+            const int r = ps * 16 + rq;
+            const int64_t i = r0 + r;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t j = c0 + cq + e;
+                const bool keep = i < n && j < n && j > i;
+                const float x = d[ps][e];
+                sm[r][cq + e] = keep ? x * x : 0.0f;
+                if (keep) st += (double)x * (double)x;
+            }
+        }
+        __syncthreads();
+        const int64_t off = unit;
+        for (int q = 0; q < 4; q++) {
+            const int idx = tid + 256 * q;
+            const int rb = idx / 256, s = (idx / 64) % 4, lane = idx % 64;
+            const int r = rb * 32 + (lane % 32);
+            const int cb = 32 * (lane / 32) + 8 * s;
+            uint32_t hw[4], lw[4];
+            for (int e2 = 0; e2 < 4; e2++) {
+                const float x0 = sm[r][cb + 2 * e2], x1 = sm[r][cb + 2 * e2 + 1];
+                if (DT == 1) {
+                    hw[e2] = (uint32_t)to_f16_bits(x0) | ((uint32_t)to_f16_bits(x1) << 16);
+                } else {
+                    const uint16_t h0 = to_bf16_bits(x0), h1 = to_bf16_bits(x1);
+                    hw[e2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                    if (DT == 2) {
+                        const uint16_t l0 = to_bf16_bits(x0 - bf16_bits_to_float(h0));
+                        const uint16_t l1 = to_bf16_bits(x1 - bf16_bits_to_float(h1));
+                        lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                    }
+                }
+            }
+            tiles[off * kUnitU4 + idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            if (DT == 2)
+                tiles[(comp_units + off) * kUnitU4 + idx] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+    }
+    if (sT_part) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) st += __shfl_xor(st, o);
+        if (tid % 64 == 0) sred[tid / 64] = st;
+        __syncthreads();
+        if (tid == 0) sT_part[blockIdx.x] = ((sred[0] + sred[1]) + sred[2]) + sred[3];
     }
 }
 
@@ -460,15 +509,24 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
 
 size_t mfma_table_bytes(const MfmaPlan &pl) { return (size_t)pl.items * 3 * sizeof(int32_t); }
 
-void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s) {
+void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
+                         double *sT_part, double *sT) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t kb_total = panels * 2;
     const int64_t comp_units = panels * (panels + 1);
-    dim3 grid((unsigned)kb_total, (unsigned)panels);
+    // one s_T partial per work-group: no more work-groups than partial slots
+    int64_t blocks = sT_partials_count(n);
+    if (blocks > comp_units) blocks = comp_units;
+    const int vec = (n % 4 == 0) && ((uintptr_t)mat % 16 == 0);
+    const dim3 grid((unsigned)blocks);
     uint4 *t = (uint4 *)tiles;
-    if (dtype == 0) hipLaunchKernelGGL(k_prepass<0>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, t);
-    else if (dtype == 1) hipLaunchKernelGGL(k_prepass<1>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, t);
-    else hipLaunchKernelGGL(k_prepass<2>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, t);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_prepass<0>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
+    else if (dtype == 1)
+        hipLaunchKernelGGL(k_prepass<1>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
+    else
+        hipLaunchKernelGGL(k_prepass<2>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
+    if (sT_part) launch_sT_final(sT_part, blocks, n, sT, s);
 }
 
 template <int DT, int NF, int LQ>

@@ -266,4 +266,8 @@ void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStr
     hipLaunchKernelGGL(k_sT_final, dim3(1), dim3(256), 0, s, partials, blocks, n, sT);
 }
 
+void launch_sT_final(const double *partials, int64_t count, int64_t n, double *sT, hipStream_t s) {
+    hipLaunchKernelGGL(k_sT_final, dim3(1), dim3(256), 0, s, partials, count, n, sT);
+}
+
 } // namespace pstat

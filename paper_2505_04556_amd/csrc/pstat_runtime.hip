@@ -186,7 +186,8 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
 
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
-            double *out, const void *tiles, int32_t *err_flag, bool timed) {
+            double *out, const void *tiles, int32_t *err_flag, bool timed, double *sT_part,
+            double *sT) {
     hipStream_t s = tls.stream;
     int rc;
     launch_fill_u8(L.bad, P, 0, s);
@@ -207,7 +208,7 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
     launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, s);
     if ((rc = check_launch("label staging"))) return rc;
     if (!tiles) {
-        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s);
+        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT);
         if ((rc = check_launch("mfma prepass"))) return rc;
         tiles = L.tiles;
     }
@@ -304,12 +305,15 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 }
 
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
-                int path, char *region, size_t region_bytes, int64_t *rechecked_out) {
+                int path, char *region, size_t region_bytes, int64_t *rechecked_out,
+                bool sT_ready) {
     hipStream_t s = tls.stream;
     int rc;
     const int64_t R = n_perms + 1;
-    launch_sT(mat, n, h.sTp, h.sT, s);
-    if ((rc = check_launch("s_T"))) return rc;
+    if (!sT_ready) {
+        launch_sT(mat, n, h.sTp, h.sT, s);
+        if ((rc = check_launch("s_T"))) return rc;
+    }
     // FP64 recheck.  First the observed grouping and the first few
     // permutations: the observed value gives F_obs, and the largest relative
     // error of the fast path over these samples sets the tie band.  Then every
@@ -574,11 +578,15 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         Carver c{ws + head, region, 0, false};
         SwLayout L;
         layout_sW(c, n, R, k, path, true, L);
-        if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags)))
+        // the MFMA forms' pre-pass also leaves s_T
+        if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags, true,
+                          h.sTp, h.sT)))
             return rc;
     }
     int64_t rechecked = 0;
-    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head, region, &rechecked))) return rc;
+    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head, region, &rechecked,
+                          is_mfma(path))))
+        return rc;
     (void)s;
     if (n_rechecked) *n_rechecked = rechecked;
     return PSTAT_OK;

@@ -125,7 +125,8 @@ struct KernelTimer {
 
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
-            double *out, const void *tiles, int32_t *err_flag, bool timed = true);
+            double *out, const void *tiles, int32_t *err_flag, bool timed = true,
+            double *sT_part = nullptr, double *sT = nullptr);
 int scan_labels_sync(const int32_t *g, int64_t count, int32_t limit, int32_t *max_label);
 
 // ---- the whole permutation test in phases ------------------------------------
@@ -151,8 +152,10 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 // After h.sw holds the fast path's s_W of all R rows: s_T, FP64 recheck of the
 // observed grouping, band samples and near ties, p-value, result.  `region` is
 // scratch of at least few_partial_bytes(n, R) bytes.
+// sT_ready: s_T was already left in h.sT (by the pre-pass of the MFMA forms).
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
-                int path, char *region, size_t region_bytes, int64_t *rechecked);
+                int path, char *region, size_t region_bytes, int64_t *rechecked,
+                bool sT_ready = false);
 
 // Tie band of the p-value recheck: kBandMargin times the largest relative
 // error of the fast path over the observed grouping and the first
