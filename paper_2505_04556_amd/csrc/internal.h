@@ -85,6 +85,11 @@ struct UnitDesc {             // one work-group's share of one job: plain
 size_t few_partial_bytes(int64_t n, int64_t m);
 void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
                    int32_t k, const double *w, double *partial, double *out, hipStream_t s);
+// The same with the groupings as u16 rows of `stride` entries (the MFMA
+// forms' staged labels).
+void launch_sw_few_u16(const float *mat, int64_t n, const uint16_t *g, int64_t stride,
+                       const int32_t *rows, int64_t m, int32_t k, const double *w, double *partial,
+                       double *out, hipStream_t s);
 void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                            int64_t max_units, hipStream_t s);
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
@@ -151,5 +156,10 @@ void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32
 // ---- permutation generator (k_permute.hip) -----------------------------------
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
                    int32_t *out, size_t lds_limit, hipStream_t s);
+// The same permutations written as u16 rows of `stride` entries (row p at
+// out + p * stride), padded with kPadLabel: the MFMA forms' staged layout.
+// Returns nonzero (nothing launched) when no LDS-resident form fits.
+int launch_permute_u16(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
+                       uint16_t *out, int64_t stride, size_t lds_limit, hipStream_t s);
 
 } // namespace pstat

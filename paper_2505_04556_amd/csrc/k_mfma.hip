@@ -162,18 +162,20 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
 
 // ---- work items ---------------------------------------------------------------
 // tab[3*item] = panel I, tab[3*item+1] = first K block, tab[3*item+2] = end.
-__global__ void k_item_table(int64_t panels, int64_t kb_total, int64_t kchunk,
-                             int32_t *__restrict__ tab) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Items in panel order, K chunks ascending; thread I writes panel I's items
+// after counting those of the panels before it.
+__global__ __launch_bounds__(256) void k_item_table(int64_t panels, int64_t kb_total,
+                                                    int64_t kchunk, int32_t *__restrict__ tab) {
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (I >= panels) return;
     int64_t it = 0;
-    for (int64_t I = 0; I < panels; I++) {
-        for (int64_t kb = 2 * I; kb < kb_total; kb += kchunk) {
-            const int64_t e = kb + kchunk < kb_total ? kb + kchunk : kb_total;
-            tab[3 * it] = (int32_t)I;
-            tab[3 * it + 1] = (int32_t)kb;
-            tab[3 * it + 2] = (int32_t)e;
-            it++;
-        }
+    for (int64_t J = 0; J < I; J++) it += (kb_total - 2 * J + kchunk - 1) / kchunk;
+    for (int64_t kb = 2 * I; kb < kb_total; kb += kchunk) {
+        const int64_t e = kb + kchunk < kb_total ? kb + kchunk : kb_total;
+        tab[3 * it] = (int32_t)I;
+        tab[3 * it + 1] = (int32_t)kb;
+        tab[3 * it + 2] = (int32_t)e;
+        it++;
     }
 }
 
@@ -555,7 +557,8 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
     (void)n;
     if (pl.ncols != 256 && pl.ncols != 512) return -1;
     if (k < 2 || (pl.kchunk & 1)) return -1;
-    hipLaunchKernelGGL(k_item_table, dim3(1), dim3(64), 0, s, pl.panels, pl.kb_total, pl.kchunk, tab);
+    hipLaunchKernelGGL(k_item_table, dim3((unsigned)ceil_div(pl.panels, 256)), dim3(256), 0, s,
+                       pl.panels, pl.kb_total, pl.kchunk, tab);
     const int64_t grid_real = pl.items * pl.nblocks;
     const int64_t gpad = round_up(grid_real, 8);
     const int64_t comp_units = pl.panels * (pl.panels + 1);
@@ -580,7 +583,8 @@ void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int3
 }
 
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s) {
-    hipLaunchKernelGGL(k_item_table, dim3(1), dim3(64), 0, s, pl.panels, pl.kb_total, pl.kchunk, tab);
+    hipLaunchKernelGGL(k_item_table, dim3((unsigned)ceil_div(pl.panels, 256)), dim3(256), 0, s,
+                       pl.panels, pl.kb_total, pl.kchunk, tab);
 }
 
 } // namespace pstat

@@ -159,18 +159,21 @@ struct WideStore {
             for (int q = 0; q < live; q++) arr[(int64_t)q * n + i] = b;
         }
     }
-    // Copy out, 16-byte stores when `vec`.
-    __device__ static void drain(const unsigned char *smem, int32_t *out, int64_t p0, int64_t n,
-                                 int live, int vec, int tid, int nthr) {
+    // Copy out into rows of `stride` entries: int32 rows (16-byte stores when
+    // `vec`), or u16 rows padded with kPadLabel up to the stride.
+    template <typename O>
+    __device__ static void drain(const unsigned char *smem, O *out, int64_t stride, int64_t p0,
+                                 int64_t n, int live, int vec, int tid, int nthr) {
         const E *arr = reinterpret_cast<const E *>(smem);
-        const int64_t n4 = vec ? n / 4 : 0;
+        const int64_t n4 = (vec && sizeof(O) == 4) ? n / 4 : 0;
         for (int q = 0; q < live; q++) {
             const E *src = arr + (int64_t)q * n;
-            int32_t *dst = out + (p0 + q) * n;
+            O *dst = out + (p0 + q) * stride;
             int4 *dst4 = reinterpret_cast<int4 *>(dst);
             for (int64_t v = tid; v < n4; v += nthr)
                 dst4[v] = make_int4(src[4 * v], src[4 * v + 1], src[4 * v + 2], src[4 * v + 3]);
-            for (int64_t i = 4 * n4 + tid; i < n; i += nthr) dst[i] = (int32_t)src[i];
+            for (int64_t i = 4 * n4 + tid; i < n; i += nthr) dst[i] = (O)src[i];
+            for (int64_t i = n + tid; i < stride; i += nthr) dst[i] = (O)kPadLabel;
         }
     }
 };
@@ -219,38 +222,57 @@ struct NibbleStore {
             for (int q = 0; q < live; q++) arr[(int64_t)q * nw + v] = word;
         }
     }
-    __device__ static void drain(const unsigned char *smem, int32_t *out, int64_t p0, int64_t n,
-                                 int live, int vec, int tid, int nthr) {
+    // Copy out into rows of `stride` entries: int32 rows (two 16-byte stores
+    // per word when `vec`), or u16 rows (one 16-byte store per word when
+    // `vec`) padded with kPadLabel up to the stride.
+    template <typename O>
+    __device__ static void drain(const unsigned char *smem, O *out, int64_t stride, int64_t p0,
+                                 int64_t n, int live, int vec, int tid, int nthr) {
         const uint32_t *arr = reinterpret_cast<const uint32_t *>(smem);
         const int64_t nw = (n + 7) / 8;
         for (int q = 0; q < live; q++) {
             const uint32_t *src = arr + (int64_t)q * nw;
-            int32_t *dst = out + (p0 + q) * n;
+            O *dst = out + (p0 + q) * stride;
             for (int64_t v = tid; v < nw; v += nthr) {
                 const uint32_t word = src[v];
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int64_t i0 = 8 * v + 4 * h;
-                    const uint32_t x = word >> (16 * h);
-                    if (vec && i0 + 4 <= n) {
+                const int64_t i0 = 8 * v;
+                if (vec && i0 + 8 <= n) {
+                    if constexpr (sizeof(O) == 4) {
                         *reinterpret_cast<int4 *>(dst + i0) =
-                            make_int4(x & 15u, (x >> 4) & 15u, (x >> 8) & 15u, (x >> 12) & 15u);
+                            make_int4(word & 15u, (word >> 4) & 15u, (word >> 8) & 15u,
+                                      (word >> 12) & 15u);
+                        *reinterpret_cast<int4 *>(dst + i0 + 4) =
+                            make_int4((word >> 16) & 15u, (word >> 20) & 15u, (word >> 24) & 15u,
+                                      word >> 28);
                     } else {
-                        for (int e = 0; e < 4; e++)
-                            if (i0 + e < n) dst[i0 + e] = (int32_t)((x >> (4 * e)) & 15u);
+                        // u16 pairs: nibbles 2e and 2e + 1 into one dword
+                        const uint32_t lo = word & 0x0F0F0F0Fu, hi = (word >> 4) & 0x0F0F0F0Fu;
+                        // bytes of lo: labels 0, 2, 4, 6; of hi: 1, 3, 5, 7
+                        const uint32_t d0 = (lo & 0xFFu) | ((hi & 0xFFu) << 16);
+                        const uint32_t d1 = ((lo >> 8) & 0xFFu) | (((hi >> 8) & 0xFFu) << 16);
+                        const uint32_t d2 = ((lo >> 16) & 0xFFu) | (((hi >> 16) & 0xFFu) << 16);
+                        const uint32_t d3 = (lo >> 24) | ((hi >> 24) << 16);
+                        *reinterpret_cast<uint4 *>(dst + i0) = make_uint4(d0, d1, d2, d3);
                     }
+                } else {
+                    for (int e = 0; e < 8; e++)
+                        if (i0 + e < n) dst[i0 + e] = (O)((word >> (4 * e)) & 15u);
                 }
             }
+            for (int64_t i = n + tid; i < stride; i += nthr) dst[i] = (O)kPadLabel;
         }
     }
 };
 
 // Batched shuffle: B lanes per permutation, 64 / B permutations per wave,
-// blockDim.x / 64 waves per work-group, arrays in dynamic LDS as S stores them.
-template <typename S, int B>
+// blockDim.x / 64 waves per work-group, arrays in dynamic LDS as S stores them;
+// permutation p goes to row p of `out` (O = int32 rows of n labels, or u16
+// rows of `ostride` entries padded with kPadLabel).
+template <typename S, int B, typename O>
 __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict__ base, int64_t n,
                                                        int64_t P, uint64_t seed, int apw, int vec,
-                                                       int32_t *__restrict__ out) {
+                                                       O *__restrict__ out, int64_t ostride,
+                                                       int ovec) {
     static_assert(B == 16 || B == 64, "lanes per permutation");
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -397,7 +419,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         x = xn;
     }
     __syncthreads();
-    S::drain(smem, out, p0, n, live, vec, tid, nthr);
+    S::drain(smem, out, ostride, p0, n, live, ovec, tid, nthr);
 }
 
 template <typename E>
@@ -475,9 +497,9 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
 // arrays; B = 16 lanes per permutation and 1, 2 or 4 arrays per wave when at
 // least four arrays fit, else B = 64 and one array per wave.  Work-groups
 // small enough share a CU.
-template <typename S>
-int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t *out,
-                 size_t lds_limit, hipStream_t s) {
+template <typename S, typename O>
+int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *out,
+                 int64_t ostride, size_t lds_limit, hipStream_t s) {
     const size_t row = S::row_bytes(n);
     const size_t spare = S::spare_bytes();       // the per-thread dummy slots
     if (lds_limit <= spare) return 1;
@@ -501,14 +523,17 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32
     const int64_t ppg = waves * pw;
     const size_t bytes = (size_t)ppg * row + spare;
     const int64_t blocks = ceil_div(P, ppg);
-    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    // 16-byte loads of the base labels; 16-byte stores of whole rows' words
+    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0);
+    const int ovec = (uintptr_t)out % 16 == 0 &&
+                     (sizeof(O) == 4 ? n % 4 == 0 : ostride % 8 == 0);
     const dim3 grid((unsigned)blocks), block((unsigned)(64 * waves));
 #define PSTAT_BATCH_CASE(B_)                                                                     \
     if (B == B_) {                                                                               \
-        (void)hipFuncSetAttribute((const void *)k_permute_batch<S, B_>,                          \
+        (void)hipFuncSetAttribute((const void *)k_permute_batch<S, B_, O>,                       \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);       \
-        hipLaunchKernelGGL((k_permute_batch<S, B_>), grid, block, bytes, s, base, n, P, seed, pw, \
-                           vec, out);                                                            \
+        hipLaunchKernelGGL((k_permute_batch<S, B_, O>), grid, block, bytes, s, base, n, P, seed,  \
+                           pw, vec, out, ostride, ovec);                                         \
         return 0;                                                                                \
     }
     PSTAT_BATCH_CASE(16)
@@ -522,12 +547,13 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
                    int32_t *out, size_t lds_limit, hipStream_t s) {
     if (P <= 0 || n <= 0) return 0;
-    if (max_label < 16 && launch_batch<NibbleStore>(base, n, P, seed, out, lds_limit, s) == 0)
+    if (max_label < 16 && launch_batch<NibbleStore>(base, n, P, seed, out, n, lds_limit, s) == 0)
         return 0;
-    if (max_label < 256 && launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, lds_limit, s) == 0)
+    if (max_label < 256 &&
+        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, n, lds_limit, s) == 0)
         return 0;
     if (max_label < 65536 &&
-        launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, lds_limit, s) == 0)
+        launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, n, lds_limit, s) == 0)
         return 0;
     if (max_label < 256 && launch_lds<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
     if (max_label < 65536 && launch_lds<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)
@@ -535,6 +561,21 @@ int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int
     hipLaunchKernelGGL(k_permute_global, dim3((unsigned)ceil_div(P, 64)), dim3(64), 0, s, base, n,
                        P, seed, out);
     return 0;
+}
+
+int launch_permute_u16(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
+                       uint16_t *out, int64_t stride, size_t lds_limit, hipStream_t s) {
+    if (P <= 0 || n <= 0) return 0;
+    if (stride < n || max_label >= 65535) return 1;
+    if (max_label < 16 &&
+        launch_batch<NibbleStore>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+        return 0;
+    if (max_label < 256 &&
+        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+        return 0;
+    if (launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+        return 0;
+    return 1;
 }
 
 } // namespace pstat

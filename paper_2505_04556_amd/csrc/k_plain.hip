@@ -219,10 +219,10 @@ constexpr int64_t kFewChunks = 4096;  // work-groups (tile runs) per launch
 constexpr int64_t kFewMaxM = 1024;    // groupings per launch
 constexpr int kFewWLds = 1024;        // weights kept in LDS up to this many groups
 
-template <int EQ>
+template <int EQ, typename LT>
 __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, int64_t n,
                                                 int64_t nt, int64_t tiles, int64_t tpc,
-                                                const int32_t *__restrict__ g,
+                                                const LT *__restrict__ g, int64_t gstride,
                                                 const int32_t *__restrict__ rows, int64_t m,
                                                 int32_t k, const double *__restrict__ w,
                                                 double *__restrict__ partial, int64_t m_pad) {
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
 #pragma unroll
     for (int r = 0; r < LR; r++) {
         const int64_t q = q0 + wave / 2 + 2 * r;
-        gb[r] = q < m ? (int64_t)rows[q] * n : -1;
+        gb[r] = q < m ? (int64_t)rows[q] * gstride : -1;
     }
     double acc[EQ];
 #pragma unroll
@@ -269,7 +269,8 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
         }
         const int64_t idx = (side ? J : I) * kFT + c;
 #pragma unroll
-        for (int r = 0; r < LR; r++) ln[r] = (gb[r] >= 0 && idx < n) ? g[gb[r] + idx] : -1 - side;
+        for (int r = 0; r < LR; r++)
+            ln[r] = (gb[r] >= 0 && idx < n) ? (int32_t)g[gb[r] + idx] : -1 - side;
     };
     if (t0 < t_end) fetch(t0);
     __syncthreads();   // weights in LDS
@@ -404,8 +405,10 @@ size_t few_partial_bytes(int64_t n, int64_t m) {
     return (size_t)runs * (size_t)round_up(mm, 8) * sizeof(double);
 }
 
-void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
-                   int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
+namespace {
+template <typename LT>
+void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const int32_t *rows,
+              int64_t m, int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
     const int64_t nt = ceil_div(n, kFT);
     const int64_t tiles = nt * (nt + 1) / 2;
     const int64_t runs = tiles < kFewChunks ? tiles : kFewChunks;
@@ -415,18 +418,30 @@ void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t 
         const int64_t mm = m - b < kFewMaxM ? m - b : kFewMaxM;
         const int64_t m_pad = round_up(mm, 8);
         if (mm <= 4)
-            hipLaunchKernelGGL(k_sw_few<4>, dim3((unsigned)used, 1), dim3(256), 0, s, mat, n, nt,
-                               tiles, tpc, g, rows + b, mm, k, w, partial, m_pad);
+            hipLaunchKernelGGL((k_sw_few<4, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
+                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
         else if (mm <= 8)
-            hipLaunchKernelGGL(k_sw_few<8>, dim3((unsigned)used, 1), dim3(256), 0, s, mat, n, nt,
-                               tiles, tpc, g, rows + b, mm, k, w, partial, m_pad);
+            hipLaunchKernelGGL((k_sw_few<8, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
+                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
         else
-            hipLaunchKernelGGL(k_sw_few<16>, dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
-                               dim3(256), 0, s, mat, n, nt, tiles, tpc, g, rows + b, mm, k, w,
-                               partial, m_pad);
+            hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
+                               dim3(256), 0, s, mat, n, nt, tiles, tpc, g, gstride, rows + b, mm, k,
+                               w, partial, m_pad);
         hipLaunchKernelGGL(k_reduce_few, dim3((unsigned)mm), dim3(256), 0, s, partial, used, m_pad,
                            out + b);
     }
+}
+} // namespace
+
+void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
+                   int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
+    sw_few_t(mat, n, g, n, rows, m, k, w, partial, out, s);
+}
+
+void launch_sw_few_u16(const float *mat, int64_t n, const uint16_t *g, int64_t stride,
+                       const int32_t *rows, int64_t m, int32_t k, const double *w, double *partial,
+                       double *out, hipStream_t s) {
+    sw_few_t(mat, n, g, stride, rows, m, k, w, partial, out, s);
 }
 
 } // namespace pstat

@@ -182,15 +182,17 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
 // Runs one evaluation: stage labels (row q of the staged problem is row
 // rows[q] of g, or row q when rows is NULL; rows is only used by plain paths),
 // run the kernel, reduce into out[0..P).  tiles: pre-squared tiles of a
-// registered matrix, or NULL to run the pre-pass into L.tiles.
+// registered matrix, or NULL to run the pre-pass into L.tiles (which also
+// leaves s_T in *sT when sT_part is set).  staged: L.lab and L.bad already
+// hold the MFMA forms' labels (g is then not read).
 
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
             double *out, const void *tiles, int32_t *err_flag, bool timed, double *sT_part,
-            double *sT) {
+            double *sT, bool staged) {
     hipStream_t s = tls.stream;
     int rc;
-    launch_fill_u8(L.bad, P, 0, s);
+    if (!staged) launch_fill_u8(L.bad, P, 0, s);
     if (!is_mfma(L.path)) {
         launch_stage_labels_om(g, rows, n, P, L.pp.n_pad, L.pp.P_pad, limit, L.lab, L.bad,
                                err_flag, s);
@@ -205,8 +207,10 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
         return check_launch("plain reduce");
     }
     if (rows) return fail(PSTAT_EINVAL, "row lists are only supported on the plain paths");
-    launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, s);
-    if ((rc = check_launch("label staging"))) return rc;
+    if (!staged) {
+        launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, s);
+        if ((rc = check_launch("label staging"))) return rc;
+    }
     if (!tiles) {
         launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT);
         if ((rc = check_launch("mfma prepass"))) return rc;
@@ -306,7 +310,7 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked_out,
-                bool sT_ready) {
+                bool sT_ready, const uint16_t *lab16, int64_t stride16) {
     hipStream_t s = tls.stream;
     int rc;
     const int64_t R = n_perms + 1;
@@ -324,8 +328,15 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
         const int64_t S = (n_perms < kBandSamples ? n_perms : kBandSamples) + 1;
         if (region_bytes < few_partial_bytes(n, R)) return fail(PSTAT_ENOMEM, "recheck region too small");
         double *partial = (double *)region;
+        // FP64 s_W of the groupings listed in h.list[0..m)
+        auto recheck = [&](int64_t m) {
+            if (lab16)
+                launch_sw_few_u16(mat, n, lab16, stride16, h.list, m, k, h.w, partial, h.vals, s);
+            else
+                launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s);
+        };
         launch_iota(h.list, S, s);
-        launch_sw_few(mat, n, h.allg, h.list, S, k, h.w, partial, h.vals, s);
+        recheck(S);
         if ((rc = check_launch("FP64 recheck"))) return rc;
         launch_tie_band(h.sw, h.vals, S, kBandMargin, h.band, s);
         launch_scatter(h.vals, h.list, S, h.sw, s);
@@ -341,7 +352,7 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
             m = tls.host_flags[2];
         }
         if (m > 0) {
-            launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s);
+            recheck(m);
             launch_scatter(h.vals, h.list, m, h.sw, s);
             if ((rc = check_launch("recheck"))) return rc;
         }
@@ -563,31 +574,47 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     Carver dry{nullptr, 0, 0, true};
     carve_head(dry, n, R, k, h);
     const size_t head = (size_t)round_up((int64_t)dry.used, 256) + 256;
-    size_t region = sW_bytes(n, R, k, path, true);
-    const size_t region64 = few_partial_bytes(n, R);
-    if (region64 > region) region = region64;
+    // s_W workspace, then the FP64 recheck's partials (the recheck may read
+    // the staged labels, so the two must not overlap)
+    const size_t swb = sW_bytes(n, R, k, path, true);
+    const size_t fpb = few_partial_bytes(n, R);
     char *ws;
-    if ((rc = acquire_workspace(head + region, &ws))) return rc;
+    if ((rc = acquire_workspace(head + swb + fpb, &ws))) return rc;
     Carver hc{ws, head, 0, false};
     carve_head(hc, n, R, k, h);
     if (sW_all) h.sw = sW_all;
     if (result) h.result = result;
 
-    if ((rc = prepare_test(h, n, grouping, k, n_perms, seed, max_label))) return rc;
-    {
-        Carver c{ws + head, region, 0, false};
-        SwLayout L;
-        layout_sW(c, n, R, k, path, true, L);
-        // the MFMA forms' pre-pass also leaves s_T
-        if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags, true,
-                          h.sTp, h.sT)))
-            return rc;
+    Carver c{ws + head, swb, 0, false};
+    SwLayout L;
+    layout_sW(c, n, R, k, path, true, L);
+    // MFMA forms: the shuffle writes the permutations straight into the
+    // staged u16 layout (row 0 the observed grouping, rows past R padding)
+    bool staged = false;
+    if (is_mfma(path)) {
+        const int64_t np = L.mp.n_pad;
+        launch_fill_u8(L.bad, R, 0, s);
+        staged = launch_permute_u16(grouping, n, n_perms, seed, max_label, L.lab + np, np,
+                                    dev_info().lds_limit, s) == 0;
+        if (staged) {
+            if ((rc = check_launch("permute"))) return rc;
+            launch_stage_labels_pm(grouping, n, 1, np, 1, k, L.lab, L.bad, tls.flags, s);
+            if (L.mp.P_pad > R)
+                launch_stage_labels_pm(grouping, n, 0, np, L.mp.P_pad - R, k, L.lab + R * np,
+                                       L.bad, tls.flags, s);
+            launch_group_weights(grouping, n, k, h.counts, h.w, s);
+            if ((rc = check_launch("label staging"))) return rc;
+        }
     }
-    int64_t rechecked = 0;
-    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head, region, &rechecked,
-                          is_mfma(path))))
+    if (!staged && (rc = prepare_test(h, n, grouping, k, n_perms, seed, max_label))) return rc;
+    // the MFMA forms' pre-pass also leaves s_T
+    if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags, true,
+                      h.sTp, h.sT, staged)))
         return rc;
-    (void)s;
+    int64_t rechecked = 0;
+    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head + swb, fpb, &rechecked,
+                          is_mfma(path), staged ? L.lab : nullptr, L.mp.n_pad)))
+        return rc;
     if (n_rechecked) *n_rechecked = rechecked;
     return PSTAT_OK;
 }
