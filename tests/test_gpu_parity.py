@@ -345,3 +345,32 @@ def test_permanova_matches_oracle(ps, path):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert res[1] == ref["p"], (res[1], ref["p"], rechecked)
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+
+
+# Whole test on both forms with labels of every shuffle storage width (four
+# bits below 16, one byte below 256, u16 above) and without permutations.
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16"])
+@pytest.mark.parametrize("n,k,P", [(700, 20, 300), (700, 300, 100), (600, 3, 0), (650, 16, 64)])
+def test_permanova_label_widths(ps, path, n, k, P):
+    import torch
+    rng = np.random.default_rng(n + k)
+    # uneven group sizes, every group non-empty
+    base = np.concatenate([np.arange(k), rng.integers(0, k, size=n - k)]).astype(np.int32)
+    rng.shuffle(base)
+    D = synth.uniform_matrix(n, 11 + k)
+    seed = 4242 + P
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    sw = sw.cpu().numpy()
+    if P:
+        assert max_rel(sw[1:], ref["sW_perm"]) <= TOL[path]
+        assert res[1] == ref["p"], (res[1], ref["p"], rechecked)
+    else:
+        assert np.isnan(res[1]) and np.isnan(ref["p"])   # no permutations: p undefined
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+    assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
