@@ -190,15 +190,15 @@ def recorded_traffic(kernel_src: str, summary: str):
     return float(fields["traffic_bytes_per_launch"].split()[0])
 
 
-def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
-    """The serving trace: Poisson arrivals (4 requests/s), n in {1k..20k}, k in
-    2..12 with Dirichlet sizes, 999 or 9,999 permutations; continuous batching
-    under an HBM budget.  Latency = result time - arrival time."""
+def serve_trace(budget_bytes: int, count: int, rate: float, arrival_seed: int):
+    """One serving trace: Poisson arrivals (`rate` requests/s, arrival times from
+    `arrival_seed`), n in {1k..20k}, k in 2..12 with Dirichlet sizes, 999 or
+    9,999 permutations; continuous batching under an HBM budget."""
     import synth
     import synth.device as sd
     from paper_2505_04556_amd.serve import GpuExecutor, Request, Server
     reqs = []
-    for t in synth.serving_requests(count, rate, 4000):
+    for t in synth.serving_requests(count, rate, arrival_seed):
         reqs.append(Request(id=t["id"], n=t["n"], k=t["k"], grouping=synth.base_labels(t["sizes"]),
                             n_perms=t["n_perms"], seed=t["perm_seed"], arrival=t["arrival"],
                             make_matrix=(lambda dev, n=t["n"], s=t["matrix_seed"]:
@@ -209,10 +209,20 @@ def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
         f = ex.form(r)
         forms[f] = forms.get(f, 0) + 1
     try:
+        ex.warmup(reserve_bytes=budget_bytes)   # server start-up, before the first arrival
         srv = Server(ex, hbm_budget=budget_bytes, round_work=1.5e11, max_units=8192)
         res = srv.run(reqs)
     finally:
         ex.close()
+    return res, forms
+
+
+def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0, seeds: int = 1) -> dict:
+    """The serving trace at arrival seed 4000 (latency = result time - arrival
+    time, nearest-rank quantiles); with seeds > 1 the same requests are replayed
+    under arrival seeds 4001, ... and the latencies of all traces are pooled."""
+    from paper_2505_04556_amd.serve import nearest_rank
+    res, forms = serve_trace(budget_bytes, count, rate, 4000)
     st = dict(res["stats"])
     waited = sum(1 for o in res["outcomes"].values()
                  if o.error is None and o.admitted - o.arrival > 0.05)
@@ -220,7 +230,24 @@ def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0) -> dict:
               budget_GB=round(budget_bytes / 1e9, 3), requests=count, arrivals_per_s=rate,
               admissions_delayed_50ms=waited, quantiles="nearest rank",
               path="auto: work-list kernels of both forms in each round", jobs_by_form=forms)
-    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
+    out = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
+    if seeds > 1:
+        lat = [o.latency for o in res["outcomes"].values() if o.error is None]
+        per = [dict(seed=4000, p50_s=out["p50_s"], p99_s=out["p99_s"],
+                    G_pair_perms_per_s=out["G_pair_perms_per_s"])]
+        failed = out["failed"]
+        for sd_ in range(4001, 4000 + seeds):
+            r2, _ = serve_trace(budget_bytes, count, rate, sd_)
+            lat += [o.latency for o in r2["outcomes"].values() if o.error is None]
+            failed += r2["stats"].get("failed", 0)
+            per.append(dict(seed=sd_, p50_s=round(r2["stats"]["p50_s"], 5),
+                            p99_s=round(r2["stats"]["p99_s"], 5),
+                            G_pair_perms_per_s=round(r2["stats"]["G_pair_perms_per_s"], 4)))
+        out["pooled"] = dict(arrival_seeds=list(range(4000, 4000 + seeds)), samples=len(lat),
+                             failed=failed, p50_s=round(nearest_rank(lat, 0.50), 5),
+                             p99_s=round(nearest_rank(lat, 0.99), 5), max_s=round(max(lat), 5),
+                             per_seed=per)
+    return out
 
 
 def main() -> int:
@@ -240,6 +267,9 @@ def main() -> int:
     ap.add_argument("--gemm-only", action="store_true",
                     help="measure only the vendor BF16 GEMM rate (for profiling it)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-seeds", type=int, default=1,
+                    help="replay the serving trace under this many arrival seeds and pool "
+                         "the latencies")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -314,7 +344,7 @@ def main() -> int:
     serve = None
     if not args.no_serve:
         log("serving trace: 64 requests, Poisson 4/s")
-        serve = serve_leg(int(args.serve_budget_gb * 1e9))
+        serve = serve_leg(int(args.serve_budget_gb * 1e9), seeds=args.serve_seeds)
         log(f"  serve: p50 {serve.get('p50_s')} s, p99 {serve.get('p99_s')} s, "
             f"{serve.get('G_pair_perms_per_s')} G pair-perms/s")
 

@@ -141,6 +141,35 @@ class GpuExecutor(Executor):
             self.ps.pstat_job_release(self.server, handle)
         self.live.pop(handle, None)
 
+    def warmup(self, reserve_bytes: int = 0) -> None:
+        """Start-up work that would otherwise land on the first requests: one
+        small job of each form through create, a round and finish (loads the
+        kernels and captures the round graphs), and, with reserve_bytes, one
+        allocation of that size returned to torch's caching allocator so that
+        job scratch is later carved from it instead of fresh device
+        allocations."""
+        torch = self.torch
+        if reserve_bytes > 0:
+            with torch.cuda.stream(self.stream):
+                block = torch.empty(int(reserve_bytes), dtype=torch.uint8, device=self.device)
+                del block
+        rng = np.random.default_rng(0)
+        for k in (3, 40):     # split BF16 (k <= 16) and plain under "auto"
+            n = 640
+            g = np.concatenate([np.arange(k), rng.integers(0, k, size=n - k)]).astype(np.int32)
+
+            def make(dev, n=n):
+                d = torch.rand(n, n, device=dev)
+                d = (d + d.T) * 0.5
+                d.fill_diagonal_(0.0)
+                return d
+            req = Request(id=-1, n=n, k=k, grouping=g, n_perms=63, seed=1, make_matrix=make)
+            handle, n_units, _ = self.create(req)
+            self.run_round(np.asarray([(handle, u) for u in range(n_units)], dtype=np.int64))
+            self.finish(handle)
+            self.release(handle)
+        self.stream.synchronize()
+
     def close(self) -> None:
         self.stream.synchronize()
         self.ps.pstat_serve_destroy(self.server)
@@ -214,27 +243,36 @@ class Server:
                 if nxt < len(reqs) and realtime:
                     self.sleep(max(0.0, reqs[nxt].arrival - now()))
                 continue
-            # one round: units from the oldest jobs first, within the work budget
-            pairs = []
+            # one round: units from the oldest jobs first, within the work
+            # budget; each job contributes one contiguous run of its units
+            runs = []
+            count = 0
             work = 0.0
             completing = []
             for a in active:
-                if len(pairs) >= self.max_units or (work >= self.round_work and pairs):
+                if count >= self.max_units or (work >= self.round_work and count):
                     break
-                room = self.max_units - len(pairs)
+                room = self.max_units - count
                 by_work = max(1, int((self.round_work - work) // max(a.unit_cost, 1.0)))
                 take = min(a.n_units - a.next_unit, room, by_work)
                 if take <= 0:
                     continue
-                pairs.extend((a.handle, u) for u in range(a.next_unit, a.next_unit + take))
+                runs.append((a.handle, a.next_unit, take))
+                count += take
                 a.next_unit += take
                 work += take * a.unit_cost
                 if a.next_unit == a.n_units:
                     completing.append(a)
-            if pairs:
-                self.executor.run_round(np.asarray(pairs, dtype=np.int64))
+            if runs:
+                pairs = np.empty((count, 2), dtype=np.int64)
+                at = 0
+                for h, first, take in runs:
+                    pairs[at:at + take, 0] = h
+                    pairs[at:at + take, 1] = np.arange(first, first + take, dtype=np.int64)
+                    at += take
+                self.executor.run_round(pairs)
                 rounds += 1
-                self.log.append((now(), len(pairs), len({p[0] for p in pairs})))
+                self.log.append((now(), count, len(runs)))
             for a in completing:
                 res, sw, rech = self.executor.finish(a.handle, self.keep_sW)
                 o = out[a.req.id]

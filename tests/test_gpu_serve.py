@@ -89,3 +89,16 @@ def test_admission_under_a_small_budget(ps):
     res, _ = serve(reqs, budget=budget)
     assert res["stats"]["completed"] == len(reqs)
     assert res["peak_bytes"] <= budget
+
+
+def test_executor_warmup_leaves_nothing_behind(ps):
+    from paper_2505_04556_amd.serve import GpuExecutor
+    ex = GpuExecutor(max_jobs=4, max_units=512)
+    try:
+        ex.warmup(reserve_bytes=1 << 28)
+        assert not ex.live
+        # the server still serves afterwards
+        res, _ = serve(requests()[:3])
+        assert res["stats"]["completed"] == 3
+    finally:
+        ex.close()
