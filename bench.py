@@ -79,16 +79,21 @@ def time_path(ps, torch, path, D, base, cfg, steps, warmup, tuning=None):
         _, rechecked = ps.pstat_permanova(D, base, k, P, seed, result=res, sW_all=sw)
     torch.cuda.synchronize()
     ps.pstat_profile(True)
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(steps):
+        # each whole test ends with a synchronisation (it returns the recheck count)
+        ts = time.perf_counter()
         _, rechecked = ps.pstat_permanova(D, base, k, P, seed, result=res, sW_all=sw)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kms, launches = ps.pstat_profile_read()
     ps.pstat_profile(False)
     return dict(path=path, seconds=dt, ms_per_step=dt * 1e3 / steps, kernel_ms_total=kms,
                 kernel_launches=launches, rechecked=rechecked, sW=sw.cpu().numpy(),
-                result=res.cpu().numpy())
+                result=res.cpu().numpy(), step_ms_median=float(sorted(step_ms)[len(step_ms) // 2]),
+                step_ms_best=float(min(step_ms)))
 
 
 def speedup_leg(ps, torch, sd, synth, steps=3, warmup=1):
@@ -406,6 +411,8 @@ def main() -> int:
                    "n_perms": P, "path": best},
         "roofline": roof,
         "paths": {p: {"ms_per_step": round(v["ms_per_step"], 4),
+                      "ms_per_step_median": round(v["step_ms_median"], 4),
+                      "ms_per_step_best": round(v["step_ms_best"], 4),
                       "G_pair_perms_per_s": round(pair_perms / (v["ms_per_step"] / 1e3) / 1e9, 3),
                       "kernel_ms": round(v["kernel_ms_total"] / max(1, v["kernel_launches"]), 4),
                       "F_obs": float(v["result"][0]), "p": float(v["result"][1]),

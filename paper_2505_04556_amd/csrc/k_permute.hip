@@ -122,14 +122,14 @@ struct WideStore {
     __device__ WideStore(unsigned char *smem, int64_t n, int slot, int ppg, int tid)
         : a(reinterpret_cast<E *>(smem) + (int64_t)slot * n),
           dummy(reinterpret_cast<E *>(smem) + (int64_t)ppg * n + tid) {}
-    __device__ void swap(int64_t i, int64_t j) const {
+    __device__ void swap(int32_t i, int32_t j) const {
         const E ai = a[i], aj = a[j];
         a[i] = aj;
         a[j] = ai;
     }
     // the batch's parallel swap; `between` runs after the reads are issued
     template <typename F>
-    __device__ void swap_all(bool now, int64_t i, int64_t j, F &&between) const {
+    __device__ void swap_all(bool now, int32_t i, int32_t j, F &&between) const {
         E *pa = now ? a + i : dummy;
         E *pb = now ? a + j : dummy;
         const E va = *pa, vb = *pb;
@@ -184,21 +184,19 @@ struct NibbleStore {
     uint32_t *w;   // this lane's array, eight labels per word
     __device__ NibbleStore(unsigned char *smem, int64_t n, int slot, int, int)
         : w(reinterpret_cast<uint32_t *>(smem) + (int64_t)slot * ((n + 7) / 8)) {}
-    __device__ uint32_t get(int64_t i) const { return (w[i >> 3] >> (4 * (uint32_t)(i & 7))) & 15u; }
-    __device__ void flip(int64_t i, uint32_t d) const {
-        atomicXor(&w[i >> 3], d << (4 * (uint32_t)(i & 7)));
-    }
-    __device__ void swap(int64_t i, int64_t j) const {
-        const uint32_t d = get(i) ^ get(j);
-        flip(i, d);
-        flip(j, d);
+    __device__ uint32_t get(uint32_t i) const { return (w[i >> 3] >> (4 * (i & 7))) & 15u; }
+    __device__ void flip(uint32_t i, uint32_t d) const { atomicXor(&w[i >> 3], d << (4 * (i & 7))); }
+    __device__ void swap(int32_t i, int32_t j) const {
+        const uint32_t d = get((uint32_t)i) ^ get((uint32_t)j);
+        flip((uint32_t)i, d);
+        flip((uint32_t)j, d);
     }
     template <typename F>
-    __device__ void swap_all(bool now, int64_t i, int64_t j, F &&between) const {
-        const int64_t ia = now ? i : 0, ib = now ? j : 0;
+    __device__ void swap_all(bool now, int32_t i, int32_t j, F &&between) const {
+        const uint32_t ia = now ? (uint32_t)i : 0u, ib = now ? (uint32_t)j : 0u;
         const uint32_t wa = w[ia >> 3], wb = w[ib >> 3];
         between();
-        const uint32_t sa = 4 * (uint32_t)(ia & 7), sb = 4 * (uint32_t)(ib & 7);
+        const uint32_t sa = 4 * (ia & 7), sb = 4 * (ib & 7);
         const uint32_t d = ((wa >> sa) ^ (wb >> sb)) & 15u;   // 0 for a lane with nothing to swap
         atomicXor(&w[ia >> 3], d << sa);
         atomicXor(&w[ib >> 3], d << sb);
@@ -290,19 +288,21 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
     const int gbase = (lane / B) * B;               // first lane of the group
     const S a(smem, n, mine ? slot : 0, ppg, tid);
     const uint64_t start = stream_start(seed, (uint64_t)(p0 + slot));
-    int64_t top = mine ? n - 1 : 0;                 // current i of the permutation
+    // current i of the permutation; 32-bit index arithmetic (an array that
+    // fits in LDS has far fewer than 2^31 entries)
+    int32_t top = mine ? (int32_t)(n - 1) : 0;
     // this lane's counter, start + (d + t + 1) * gamma, advanced by B draws per batch
     uint64_t ctr = start + ((uint64_t)t + 1) * kGamma;
     uint32_t x = (uint32_t)(mix64(ctr) >> 32);
     for (;;) {
         // the wave runs until all of its permutations are done
         if (__ballot(top >= 1) == 0) break;
-        const int64_t it = top - t;                  // this lane's step if nothing is rejected
+        const int32_t it = top - t;                  // this lane's step if nothing is rejected
         const bool valid = it >= 1;
         const uint32_t sb = (uint32_t)(it + 1);
         const uint64_t m = (uint64_t)x * (uint64_t)sb;
         const uint32_t lo = (uint32_t)m;
-        const int64_t j = (int64_t)(m >> 32);
+        const int32_t j = (int32_t)(m >> 32);
         bool ok = true;
         if (valid && lo < sb) ok = lo >= (uint32_t)(0u - sb) % sb;
         const uint64_t gmask = group_mask<B>(gbase);
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         // step's partner.  Swaps without conflict commute with every other
         // swap of the batch; the conflicting ones keep their order.
         const bool real = valid && j != it;
-        int64_t lowtop = top - B + 1;
+        int32_t lowtop = top - B + 1;
         if (lowtop < 1) lowtop = 1;
         // a partner on a later step's top index (top - s for some s > t)
         bool conflict = real && j >= lowtop && j < it;
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
 #pragma unroll
             for (int r = 0; r < B; r++) xs[r] = __shfl(x, gbase + r);
             if (grej && t == 0 && mine) {
-                int64_t i = top;
+                int32_t i = top;
 #pragma unroll
                 for (int r = 0; r < B; r++) {
                     if (i >= 1) {
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
                         const uint32_t lr = (uint32_t)mr;
                         // a rejected draw is consumed and the step keeps its bound
                         if (!(lr < sr && lr < (uint32_t)(0u - sr) % sr)) {
-                            a.swap(i, (int64_t)(mr >> 32));
+                            a.swap(i, (int32_t)(mr >> 32));
                             --i;
                         }
                     }
