@@ -14,13 +14,17 @@
 // A wave holds 64 / B arrays in LDS and advances each by B steps per batch:
 // lane t of a permutation's group computes draw d + t, the step it would
 // serve if no draw of the batch is rejected (top index i - t, bound i - t + 1)
-// and its swap partner j_t.  When no draw is rejected and the B swaps touch
-// pairwise different positions (no j_t falls on another step's top index or
-// on another j), the swaps commute and the group performs them in parallel:
-// one LDS round trip instead of B.  Otherwise the group's first lane replays
-// the batch's draws in order -- exactly the sequential algorithm, rejections
-// included.  Each batch consumes B draws per permutation either way, so the
-// result is bit-identical to the one-lane-per-permutation form.
+// and its swap partner j_t.  A swap whose two positions no other swap of the
+// batch touches commutes with all of them, so those swaps run at once (one
+// LDS round trip); the others then run one at a time in step order, which
+// leaves the array exactly as the sequential order does.  A rejected draw
+// shifts every later step of its batch onto another draw, so such a batch is
+// replayed by the group's first lane in order, rejections included.  Each
+// batch consumes B draws per permutation either way, so the result is
+// bit-identical to the one-lane-per-permutation form.  Labels below 16 are
+// stored four bits to an entry (eight per LDS word, swapped with atomic xor),
+// else one byte or one u16; the output is int32 rows, or u16 rows padded to
+// a stride (the MFMA forms' staged layout).
 //
 // Fallbacks: one lane per permutation with the arrays in LDS, or in place in
 // the output when not even one array fits.
