@@ -30,9 +30,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 # Plain VALU kernel: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz single (non-packed)
-# lane operations per second; the kernel spends 3 per pair-permutation.
+# lane operations per second; the FP32 kernel spends 2 per pair-permutation (a
+# compare into a lane mask, and the add that mask enables), plus one scalar
+# move of the mask into EXEC per 64 lanes.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-PLAIN_OPS_PER_PAIRPERM = 3
+PLAIN_OPS_PER_PAIRPERM = 2
 
 
 def log(msg: str) -> None:

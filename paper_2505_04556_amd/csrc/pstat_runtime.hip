@@ -123,8 +123,8 @@ int mfma_dtype(int path) {
 
 // Default form for a shape when the thread asked for PSTAT_PATH_AUTO (the
 // autotuner's per-shape choices are applied through pstat_set_path): the MFMA
-// contraction costs 4k flops per pair-permutation in split BF16 against about
-// three VALU operations for the plain kernel at 1/64 of the matrix-core rate,
+// contraction costs 4k flops per pair-permutation in split BF16 against two
+// VALU operations for the plain kernel at 1/64 of the matrix-core rate,
 // so it wins while k stays small; tiny matrices stay on the plain kernel.
 int resolve_path(int path, int64_t n, int32_t k) {
     if (path == PSTAT_PATH_AUTO)
