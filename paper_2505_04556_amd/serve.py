@@ -82,7 +82,7 @@ class GpuExecutor(Executor):
     pair-permutations, so one round budget covers both forms: an MFMA unit's
     pair-permutations count ``mfma_speedup`` times less."""
 
-    mfma_speedup = 6.0     # split-BF16 MFMA vs plain FP32 throughput, n >= 5,000
+    mfma_speedup = 3.5     # split-BF16 MFMA vs plain FP32 throughput, n >= 5,000, k = 5
 
     def __init__(self, max_jobs: int = 64, max_units: int = 8192, device=None,
                  path: str = "auto"):
