@@ -9,7 +9,7 @@
 // wave (broadcast), so a staged tile is reused by all LANES permutations and D
 // streams from HBM once per LANES permutations instead of once per
 // permutation.  Per row segment the matching d^2 are summed in Acc (FP32 or
-// FP64; in FP32 each add runs under a lane mask set by its label compare) and
+// FP64; each add runs under a lane mask set by its label compare) and
 // then multiplied once by that row's group weight in FP64 --
 // Algorithm 2's hoisting of inv_group_sizes -- into a per-lane FP64 total.
 // Lanes never share a sum, so no cross-lane reduction is needed; each
@@ -56,8 +56,8 @@ __device__ inline double square<double>(float d) { return (double)d * (double)d;
 // acc += d[c] for each c < 16 with lc[c] == li, in column order: the 16
 // compares write lane masks, then each mask in turn becomes EXEC for one add.
 // EXEC is restored before the statement ends.
-__device__ inline void plain_masked_add16(float &acc, uint32_t li, const uint32_t *lc,
-                                          const float *d) {
+__device__ inline void masked_add16(float &acc, uint32_t li, const uint32_t *lc,
+                                    const float *d) {
     uint64_t m[16], sv;
     asm volatile(
         "v_cmp_eq_u32_e64 %[m0], %[li], %[c0]\n"
@@ -112,6 +112,65 @@ __device__ inline void plain_masked_add16(float &acc, uint32_t li, const uint32_
         "s_mov_b64 exec, %[sv]\n"
         : [acc] "+v"(acc), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [m8] "=&s"(m[8]), [m9] "=&s"(m[9]), [m10] "=&s"(m[10]), [m11] "=&s"(m[11]), [m12] "=&s"(m[12]), [m13] "=&s"(m[13]), [m14] "=&s"(m[14]), [m15] "=&s"(m[15]), [sv] "=&s"(sv)
         : [li] "v"(li), [c0] "v"(lc[0]), [c1] "v"(lc[1]), [c2] "v"(lc[2]), [c3] "v"(lc[3]), [c4] "v"(lc[4]), [c5] "v"(lc[5]), [c6] "v"(lc[6]), [c7] "v"(lc[7]), [c8] "v"(lc[8]), [c9] "v"(lc[9]), [c10] "v"(lc[10]), [c11] "v"(lc[11]), [c12] "v"(lc[12]), [c13] "v"(lc[13]), [c14] "v"(lc[14]), [c15] "v"(lc[15]), [d0] "v"(d[0]), [d1] "v"(d[1]), [d2] "v"(d[2]), [d3] "v"(d[3]), [d4] "v"(d[4]), [d5] "v"(d[5]), [d6] "v"(d[6]), [d7] "v"(d[7]), [d8] "v"(d[8]), [d9] "v"(d[9]), [d10] "v"(d[10]), [d11] "v"(d[11]), [d12] "v"(d[12]), [d13] "v"(d[13]), [d14] "v"(d[14]), [d15] "v"(d[15]));
+}
+
+// The same in FP64: sum += d[u] for each u < 16 with li[u] == lc, in order.
+__device__ inline void masked_add16(double &sum, uint32_t lc, const uint32_t *li,
+                                    const double *d) {
+    uint64_t m[16], sv;
+    asm volatile(
+        "v_cmp_eq_u32_e64 %[m0], %[lc], %[l0]\n"
+        "v_cmp_eq_u32_e64 %[m1], %[lc], %[l1]\n"
+        "v_cmp_eq_u32_e64 %[m2], %[lc], %[l2]\n"
+        "v_cmp_eq_u32_e64 %[m3], %[lc], %[l3]\n"
+        "v_cmp_eq_u32_e64 %[m4], %[lc], %[l4]\n"
+        "v_cmp_eq_u32_e64 %[m5], %[lc], %[l5]\n"
+        "v_cmp_eq_u32_e64 %[m6], %[lc], %[l6]\n"
+        "v_cmp_eq_u32_e64 %[m7], %[lc], %[l7]\n"
+        "v_cmp_eq_u32_e64 %[m8], %[lc], %[l8]\n"
+        "v_cmp_eq_u32_e64 %[m9], %[lc], %[l9]\n"
+        "v_cmp_eq_u32_e64 %[m10], %[lc], %[l10]\n"
+        "v_cmp_eq_u32_e64 %[m11], %[lc], %[l11]\n"
+        "v_cmp_eq_u32_e64 %[m12], %[lc], %[l12]\n"
+        "v_cmp_eq_u32_e64 %[m13], %[lc], %[l13]\n"
+        "v_cmp_eq_u32_e64 %[m14], %[lc], %[l14]\n"
+        "v_cmp_eq_u32_e64 %[m15], %[lc], %[l15]\n"
+        "s_mov_b64 %[sv], exec\n"
+        "s_mov_b64 exec, %[m0]\n"
+        "v_add_f64 %[sum], %[sum], %[d0]\n"
+        "s_mov_b64 exec, %[m1]\n"
+        "v_add_f64 %[sum], %[sum], %[d1]\n"
+        "s_mov_b64 exec, %[m2]\n"
+        "v_add_f64 %[sum], %[sum], %[d2]\n"
+        "s_mov_b64 exec, %[m3]\n"
+        "v_add_f64 %[sum], %[sum], %[d3]\n"
+        "s_mov_b64 exec, %[m4]\n"
+        "v_add_f64 %[sum], %[sum], %[d4]\n"
+        "s_mov_b64 exec, %[m5]\n"
+        "v_add_f64 %[sum], %[sum], %[d5]\n"
+        "s_mov_b64 exec, %[m6]\n"
+        "v_add_f64 %[sum], %[sum], %[d6]\n"
+        "s_mov_b64 exec, %[m7]\n"
+        "v_add_f64 %[sum], %[sum], %[d7]\n"
+        "s_mov_b64 exec, %[m8]\n"
+        "v_add_f64 %[sum], %[sum], %[d8]\n"
+        "s_mov_b64 exec, %[m9]\n"
+        "v_add_f64 %[sum], %[sum], %[d9]\n"
+        "s_mov_b64 exec, %[m10]\n"
+        "v_add_f64 %[sum], %[sum], %[d10]\n"
+        "s_mov_b64 exec, %[m11]\n"
+        "v_add_f64 %[sum], %[sum], %[d11]\n"
+        "s_mov_b64 exec, %[m12]\n"
+        "v_add_f64 %[sum], %[sum], %[d12]\n"
+        "s_mov_b64 exec, %[m13]\n"
+        "v_add_f64 %[sum], %[sum], %[d13]\n"
+        "s_mov_b64 exec, %[m14]\n"
+        "v_add_f64 %[sum], %[sum], %[d14]\n"
+        "s_mov_b64 exec, %[m15]\n"
+        "v_add_f64 %[sum], %[sum], %[d15]\n"
+        "s_mov_b64 exec, %[sv]\n"
+        : [sum] "+v"(sum), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [m8] "=&s"(m[8]), [m9] "=&s"(m[9]), [m10] "=&s"(m[10]), [m11] "=&s"(m[11]), [m12] "=&s"(m[12]), [m13] "=&s"(m[13]), [m14] "=&s"(m[14]), [m15] "=&s"(m[15]), [sv] "=&s"(sv)
+        : [lc] "v"(lc), [l0] "v"(li[0]), [l1] "v"(li[1]), [l2] "v"(li[2]), [l3] "v"(li[3]), [l4] "v"(li[4]), [l5] "v"(li[5]), [l6] "v"(li[6]), [l7] "v"(li[7]), [l8] "v"(li[8]), [l9] "v"(li[9]), [l10] "v"(li[10]), [l11] "v"(li[11]), [l12] "v"(li[12]), [l13] "v"(li[13]), [l14] "v"(li[14]), [l15] "v"(li[15]), [d0] "v"(d[0]), [d1] "v"(d[1]), [d2] "v"(d[2]), [d3] "v"(d[3]), [d4] "v"(d[4]), [d5] "v"(d[5]), [d6] "v"(d[6]), [d7] "v"(d[7]), [d8] "v"(d[8]), [d9] "v"(d[9]), [d10] "v"(d[10]), [d11] "v"(d[11]), [d12] "v"(d[12]), [d13] "v"(d[13]), [d14] "v"(d[14]), [d15] "v"(d[15]));
 }
 
 template <int T, int LANES, typename Acc>
@@ -192,19 +251,13 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int6
                 for (int c = 0; c < T; c++) asm volatile("" : "+v"(d[c]));
                 asm volatile("" : "+v"(li));
                 Acc acc = Acc(0);
-                if constexpr (sizeof(Acc) == 4) {
-                    static_assert(T % 16 == 0, "masked adds take 16 columns at a time");
-                    // FP32: the matching d^2 are added under an execution mask
-                    // (compares into lane masks, then per column the mask
-                    // becomes EXEC and one add runs): two vector operations
-                    // and one scalar move per pair-permutation instead of
-                    // three vector operations (compare, select, add).
+                // The matching d^2 are added under an execution mask
+                // (compares into lane masks, then per column the mask becomes
+                // EXEC and one add runs): two vector operations and one scalar
+                // move per pair-permutation instead of compare, select, add.
+                static_assert(T % 16 == 0, "masked adds take 16 columns at a time");
 #pragma unroll
-                    for (int c = 0; c < T; c += 16) plain_masked_add16(acc, li, &Lc[c], &d[c]);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < T; c++) acc += (li == Lc[c]) ? d[c] : Acc(0);
-                }
+                for (int c = 0; c < T; c += 16) masked_add16(acc, li, &Lc[c], &d[c]);
                 // weights from LDS (k <= kWeightCache), else from global memory;
                 // padding rows (label kPadLabel >= k) weigh 0
                 double wv = 0.0;
@@ -279,8 +332,8 @@ void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t
 // pairs (one column, every fourth row), holds their d^2 in FP64 registers, and
 // for each of EQ groupings adds the d^2 of its pairs whose two labels agree,
 // times that label's weight (Algorithm 1's sum, split by column).  D is read
-// once for all EQ groupings.  A pair counts through an FMA with an exact 0 or
-// 1 factor (compare, select of the factor's upper word, FMA), and each thread
+// once for all EQ groupings.  A pair counts through an add that runs under
+// the lane mask of its label compare (two vector operations), and each thread
 // keeps one running FP64 sum per grouping over the whole run of tiles; the
 // cross-lane sums happen once per work-group.  The D entries and labels of
 // the next tile are loaded while the current one is computed.  Every sum has
@@ -368,7 +421,7 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
         for (int q = 0; q < EQ; q++) {
             const int32_t lc = scol[q][c];
             const int4 *rl = reinterpret_cast<const int4 *>(&srow[q][wave][0]);
-            int32_t li[16];
+            uint32_t li[16];
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int4 r4 = rl[v];
@@ -378,11 +431,7 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
                 li[4 * v + 3] = r4.w;
             }
             double sum = 0.0;
-#pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const int hi = li[u] == lc ? 0x3FF00000 : 0;   // upper word of 1.0 or 0.0
-                sum = __builtin_fma(__hiloint2double(hi, 0), d2[u], sum);
-            }
+            masked_add16(sum, (uint32_t)lc, li, d2);
             acc[q] = __builtin_fma(sum, swc[q][c], acc[q]);
         }
         __syncthreads();   // this tile's labels are no longer read
