@@ -90,6 +90,9 @@ void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t 
 void launch_sw_few_u16(const float *mat, int64_t n, const uint16_t *g, int64_t stride,
                        const int32_t *rows, int64_t m, int32_t k, const double *w, double *partial,
                        double *out, hipStream_t s);
+// out[q] = sum over r < runs, ascending, of partial[r * stride + q], q < m.
+void launch_reduce_partials(const double *partial, int64_t runs, int64_t stride, int64_t m,
+                            double *out, hipStream_t s);
 void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                            int64_t max_units, hipStream_t s);
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
@@ -118,10 +121,26 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
                    int n_cu);
 size_t mfma_tile_bytes(int64_t n, int dtype);
 // Pre-pass: strict-upper d^2 of 128-row panels into MFMA fragment order.
+// FP64 s_W of rows 0 .. m-1 (m <= kRecheckRows) of a staged u16 label table
+// (rows of `stride` entries), computed inside the MFMA pre-pass; part holds
+// prepass_blocks(n) * kRecheckRows doubles, out[q] receives row q's s_W.
+constexpr int kRecheckRows = 16;
+struct PrepassRecheck {
+    const uint16_t *lab = nullptr;
+    int64_t stride = 0;
+    int32_t m = 0;
+    const double *w = nullptr;
+    int32_t k = 0;
+    double *part = nullptr;
+    double *out = nullptr;
+};
 // Pre-squares the strict upper triangle into MFMA fragment order; with
-// sT_part (sT_partials_count(n) doubles) set it also leaves s_T in *sT.
+// sT_part (sT_partials_count(n) doubles) set it also leaves s_T in *sT, and
+// with rc the FP64 s_W of rc->m staged label rows in rc->out.
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
-                         double *sT_part = nullptr, double *sT = nullptr);
+                         double *sT_part = nullptr, double *sT = nullptr,
+                         const PrepassRecheck *rc = nullptr);
+int64_t prepass_blocks(int64_t n);
 size_t mfma_table_bytes(const MfmaPlan &pl);
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);
 // z[item][P][k] FP32 sums of the (G^T U G) diagonal per (panel, K chunk) item;

@@ -23,6 +23,7 @@
 #include <hip/hip_bf16.h>
 
 #include "internal.h"
+#include "lane_mask.h"
 
 namespace pstat {
 
@@ -79,17 +80,35 @@ __device__ inline int64_t unit_panel(int64_t unit, int64_t kb_total) {
     return I;
 }
 
-template <int DT>
+// With RC the same pass also takes the FP64 s_W of the first rc.m (<= 16)
+// rows of the staged label table -- the observed grouping and the first
+// permutations, which the p-value recheck needs anyway -- so D is read once
+// for both.  Each thread holds its 8 x 4 block entries as exact FP64 squares;
+// per grouping and column it adds the squares of the rows whose label equals
+// the column's (masked adds, rows in order), times the column label's weight,
+// into one running FP64 sum per grouping; the sums are reduced like s_T and
+// written as one partial per work-group and grouping.
+template <int DT, bool RC>
 __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, int64_t n,
                                                  int64_t kb_total, int64_t comp_units, int vec,
                                                  uint4 *__restrict__ tiles,
-                                                 double *__restrict__ sT_part) {
+                                                 double *__restrict__ sT_part, PrepassRecheck rc) {
+    constexpr int Q = RC ? kRecheckRows : 1;
     __shared__ float sm[kPanel][kKBlock + 1];
     __shared__ double sred[4];
+    // recheck labels: rows as [grouping][row % 16][row / 16] (a thread's 8
+    // rows are contiguous), columns and their weights as [grouping][column]
+    __shared__ __align__(16) uint32_t rrow[Q][16][8];
+    __shared__ __align__(16) uint32_t rcol[Q][kKBlock];
+    __shared__ __align__(16) double rw[Q][kKBlock];
+    __shared__ double rred[RC ? 4 : 1][Q];
     const int tid = threadIdx.x;
     const int cq = (tid % 16) * 4;   // four columns of the block
     const int rq = tid / 16;         // row within each pass of 16 rows
     double st = 0.0;
+    double acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) acc[q] = 0.0;
     for (int64_t unit = blockIdx.x; unit < comp_units; unit += gridDim.x) {
         const int64_t I = unit_panel(unit, kb_total);
         const int64_t kb = 2 * I + (unit - I * (kb_total - I + 1));
@@ -110,7 +129,21 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                     d[ps][e] = (i < n && j0 + e < n) ? mat[(uint64_t)i * (uint64_t)n + j0 + e] : 0.0f;
             }
         }
+        // recheck labels of the unit: thread t loads 8 row labels of grouping
+        // t / 16 and, for t < 128, 8 column labels of grouping t / 8 (16-byte
+        // reads; the staged rows are padded to a multiple of 128 entries)
+        uint4 lr = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), lc = lr;
+        if constexpr (RC) {
+            const int qr = tid / 16, qc = tid / 8;
+            if (qr < rc.m)
+                lr = *reinterpret_cast<const uint4 *>(rc.lab + qr * rc.stride + r0 + (tid % 16) * 8);
+            if (tid < 128 && qc < rc.m)
+                lc = *reinterpret_cast<const uint4 *>(rc.lab + qc * rc.stride + c0 + (tid % 8) * 8);
+        }
         __syncthreads();   // the previous unit's LDS reads are done
+        // squares: FP32 into LDS for the fragments; exact FP64 for s_T and
+        // the recheck (0 off the strict upper triangle)
+        double d2[4][8];
 #pragma unroll
         for (int ps = 0; ps < 8; ps++) {
             const int r = ps * 16 + rq;
@@ -121,10 +154,50 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                 const bool keep = i < n && j < n && j > i;
                 const float x = d[ps][e];
                 sm[r][cq + e] = keep ? x * x : 0.0f;
-                if (keep) st += (double)x * (double)x;
+                const double xx = keep ? (double)x * (double)x : 0.0;
+                st += xx;
+                d2[e][ps] = xx;
+            }
+        }
+        if constexpr (RC) {
+            const uint32_t l8[4] = {lr.x, lr.y, lr.z, lr.w};
+            const int qr = tid / 16, rb = (tid % 16) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int r = rb + e;
+                rrow[qr][r % 16][r / 16] = (l8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+            }
+            if (tid < 128) {
+                const uint32_t c8[4] = {lc.x, lc.y, lc.z, lc.w};
+                const int qc = tid / 8, cb = (tid % 8) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const uint32_t l = (c8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+                    rcol[qc][cb + e] = l;
+                    rw[qc][cb + e] = (l < (uint32_t)rc.k) ? rc.w[l] : 0.0;
+                }
             }
         }
         __syncthreads();
+        if constexpr (RC) {
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const uint4 ra = *reinterpret_cast<const uint4 *>(&rrow[q][rq][0]);
+                const uint4 rb = *reinterpret_cast<const uint4 *>(&rrow[q][rq][4]);
+                const uint32_t rl[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+                const uint4 cl = *reinterpret_cast<const uint4 *>(&rcol[q][cq]);
+                const double2 w01 = *reinterpret_cast<const double2 *>(&rw[q][cq]);
+                const double2 w23 = *reinterpret_cast<const double2 *>(&rw[q][cq + 2]);
+                const uint32_t cls[4] = {cl.x, cl.y, cl.z, cl.w};
+                const double ws[4] = {w01.x, w01.y, w23.x, w23.y};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    double sum = 0.0;
+                    masked_add8(sum, cls[e], rl, d2[e]);
+                    acc[q] = __builtin_fma(sum, ws[e], acc[q]);
+                }
+            }
+        }
         const int64_t off = unit;
         for (int q = 0; q < 4; q++) {
             const int idx = tid + 256 * q;
@@ -157,6 +230,19 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
         if (tid % 64 == 0) sred[tid / 64] = st;
         __syncthreads();
         if (tid == 0) sT_part[blockIdx.x] = ((sred[0] + sred[1]) + sred[2]) + sred[3];
+    }
+    if constexpr (RC) {
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            double v = acc[q];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            if (tid % 64 == 0) rred[tid / 64][q] = v;
+        }
+        __syncthreads();
+        if (tid < Q)
+            rc.part[(int64_t)blockIdx.x * Q + tid] =
+                ((rred[0][tid] + rred[1][tid]) + rred[2][tid]) + rred[3][tid];
     }
 }
 
@@ -512,23 +598,38 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
 size_t mfma_table_bytes(const MfmaPlan &pl) { return (size_t)pl.items * 3 * sizeof(int32_t); }
 
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
-                         double *sT_part, double *sT) {
+                         double *sT_part, double *sT, const PrepassRecheck *rc) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t kb_total = panels * 2;
     const int64_t comp_units = panels * (panels + 1);
     // one s_T partial per work-group: no more work-groups than partial slots
-    int64_t blocks = sT_partials_count(n);
-    if (blocks > comp_units) blocks = comp_units;
+    const int64_t blocks = prepass_blocks(n);
     const int vec = (n % 4 == 0) && ((uintptr_t)mat % 16 == 0);
     const dim3 grid((unsigned)blocks);
     uint4 *t = (uint4 *)tiles;
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_prepass<0>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
-    else if (dtype == 1)
-        hipLaunchKernelGGL(k_prepass<1>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
-    else
-        hipLaunchKernelGGL(k_prepass<2>, grid, dim3(256), 0, s, mat, n, kb_total, comp_units, vec, t, sT_part);
+    const PrepassRecheck none{};
+#define PSTAT_PREPASS(DT_, RC_)                                                                   \
+    hipLaunchKernelGGL((k_prepass<DT_, RC_>), grid, dim3(256), 0, s, mat, n, kb_total, comp_units, \
+                       vec, t, sT_part, rc ? *rc : none)
+    if (rc) {
+        if (dtype == 0) PSTAT_PREPASS(0, true);
+        else if (dtype == 1) PSTAT_PREPASS(1, true);
+        else PSTAT_PREPASS(2, true);
+    } else {
+        if (dtype == 0) PSTAT_PREPASS(0, false);
+        else if (dtype == 1) PSTAT_PREPASS(1, false);
+        else PSTAT_PREPASS(2, false);
+    }
+#undef PSTAT_PREPASS
     if (sT_part) launch_sT_final(sT_part, blocks, n, sT, s);
+    if (rc) launch_reduce_partials(rc->part, blocks, kRecheckRows, rc->m, rc->out, s);
+}
+
+int64_t prepass_blocks(int64_t n) {
+    const int64_t panels = ceil_div(n, kPanel);
+    const int64_t comp_units = panels * (panels + 1);
+    const int64_t b = sT_partials_count(n);
+    return b < comp_units ? b : comp_units;
 }
 
 template <int DT, int NF, int LQ>

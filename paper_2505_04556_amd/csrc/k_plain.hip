@@ -16,6 +16,7 @@
 // work-group writes one FP64 partial per permutation and a fixed-order FP64
 // reduction combines them.
 #include "internal.h"
+#include "lane_mask.h"
 
 namespace pstat {
 
@@ -53,126 +54,6 @@ __device__ inline double square<double>(float d) { return (double)d * (double)d;
 
 // One work unit: tile chunk `chunk` of the triangle for the LANES permutations
 // of group `pg`; writes partial[chunk * P_pad + pg * LANES + lane].
-// acc += d[c] for each c < 16 with lc[c] == li, in column order: the 16
-// compares write lane masks, then each mask in turn becomes EXEC for one add.
-// EXEC is restored before the statement ends.
-__device__ inline void masked_add16(float &acc, uint32_t li, const uint32_t *lc,
-                                    const float *d) {
-    uint64_t m[16], sv;
-    asm volatile(
-        "v_cmp_eq_u32_e64 %[m0], %[li], %[c0]\n"
-        "v_cmp_eq_u32_e64 %[m1], %[li], %[c1]\n"
-        "v_cmp_eq_u32_e64 %[m2], %[li], %[c2]\n"
-        "v_cmp_eq_u32_e64 %[m3], %[li], %[c3]\n"
-        "v_cmp_eq_u32_e64 %[m4], %[li], %[c4]\n"
-        "v_cmp_eq_u32_e64 %[m5], %[li], %[c5]\n"
-        "v_cmp_eq_u32_e64 %[m6], %[li], %[c6]\n"
-        "v_cmp_eq_u32_e64 %[m7], %[li], %[c7]\n"
-        "v_cmp_eq_u32_e64 %[m8], %[li], %[c8]\n"
-        "v_cmp_eq_u32_e64 %[m9], %[li], %[c9]\n"
-        "v_cmp_eq_u32_e64 %[m10], %[li], %[c10]\n"
-        "v_cmp_eq_u32_e64 %[m11], %[li], %[c11]\n"
-        "v_cmp_eq_u32_e64 %[m12], %[li], %[c12]\n"
-        "v_cmp_eq_u32_e64 %[m13], %[li], %[c13]\n"
-        "v_cmp_eq_u32_e64 %[m14], %[li], %[c14]\n"
-        "v_cmp_eq_u32_e64 %[m15], %[li], %[c15]\n"
-        "s_mov_b64 %[sv], exec\n"
-        "s_mov_b64 exec, %[m0]\n"
-        "v_add_f32 %[acc], %[acc], %[d0]\n"
-        "s_mov_b64 exec, %[m1]\n"
-        "v_add_f32 %[acc], %[acc], %[d1]\n"
-        "s_mov_b64 exec, %[m2]\n"
-        "v_add_f32 %[acc], %[acc], %[d2]\n"
-        "s_mov_b64 exec, %[m3]\n"
-        "v_add_f32 %[acc], %[acc], %[d3]\n"
-        "s_mov_b64 exec, %[m4]\n"
-        "v_add_f32 %[acc], %[acc], %[d4]\n"
-        "s_mov_b64 exec, %[m5]\n"
-        "v_add_f32 %[acc], %[acc], %[d5]\n"
-        "s_mov_b64 exec, %[m6]\n"
-        "v_add_f32 %[acc], %[acc], %[d6]\n"
-        "s_mov_b64 exec, %[m7]\n"
-        "v_add_f32 %[acc], %[acc], %[d7]\n"
-        "s_mov_b64 exec, %[m8]\n"
-        "v_add_f32 %[acc], %[acc], %[d8]\n"
-        "s_mov_b64 exec, %[m9]\n"
-        "v_add_f32 %[acc], %[acc], %[d9]\n"
-        "s_mov_b64 exec, %[m10]\n"
-        "v_add_f32 %[acc], %[acc], %[d10]\n"
-        "s_mov_b64 exec, %[m11]\n"
-        "v_add_f32 %[acc], %[acc], %[d11]\n"
-        "s_mov_b64 exec, %[m12]\n"
-        "v_add_f32 %[acc], %[acc], %[d12]\n"
-        "s_mov_b64 exec, %[m13]\n"
-        "v_add_f32 %[acc], %[acc], %[d13]\n"
-        "s_mov_b64 exec, %[m14]\n"
-        "v_add_f32 %[acc], %[acc], %[d14]\n"
-        "s_mov_b64 exec, %[m15]\n"
-        "v_add_f32 %[acc], %[acc], %[d15]\n"
-        "s_mov_b64 exec, %[sv]\n"
-        : [acc] "+v"(acc), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [m8] "=&s"(m[8]), [m9] "=&s"(m[9]), [m10] "=&s"(m[10]), [m11] "=&s"(m[11]), [m12] "=&s"(m[12]), [m13] "=&s"(m[13]), [m14] "=&s"(m[14]), [m15] "=&s"(m[15]), [sv] "=&s"(sv)
-        : [li] "v"(li), [c0] "v"(lc[0]), [c1] "v"(lc[1]), [c2] "v"(lc[2]), [c3] "v"(lc[3]), [c4] "v"(lc[4]), [c5] "v"(lc[5]), [c6] "v"(lc[6]), [c7] "v"(lc[7]), [c8] "v"(lc[8]), [c9] "v"(lc[9]), [c10] "v"(lc[10]), [c11] "v"(lc[11]), [c12] "v"(lc[12]), [c13] "v"(lc[13]), [c14] "v"(lc[14]), [c15] "v"(lc[15]), [d0] "v"(d[0]), [d1] "v"(d[1]), [d2] "v"(d[2]), [d3] "v"(d[3]), [d4] "v"(d[4]), [d5] "v"(d[5]), [d6] "v"(d[6]), [d7] "v"(d[7]), [d8] "v"(d[8]), [d9] "v"(d[9]), [d10] "v"(d[10]), [d11] "v"(d[11]), [d12] "v"(d[12]), [d13] "v"(d[13]), [d14] "v"(d[14]), [d15] "v"(d[15]));
-}
-
-// The same in FP64: sum += d[u] for each u < 16 with li[u] == lc, in order.
-__device__ inline void masked_add16(double &sum, uint32_t lc, const uint32_t *li,
-                                    const double *d) {
-    uint64_t m[16], sv;
-    asm volatile(
-        "v_cmp_eq_u32_e64 %[m0], %[lc], %[l0]\n"
-        "v_cmp_eq_u32_e64 %[m1], %[lc], %[l1]\n"
-        "v_cmp_eq_u32_e64 %[m2], %[lc], %[l2]\n"
-        "v_cmp_eq_u32_e64 %[m3], %[lc], %[l3]\n"
-        "v_cmp_eq_u32_e64 %[m4], %[lc], %[l4]\n"
-        "v_cmp_eq_u32_e64 %[m5], %[lc], %[l5]\n"
-        "v_cmp_eq_u32_e64 %[m6], %[lc], %[l6]\n"
-        "v_cmp_eq_u32_e64 %[m7], %[lc], %[l7]\n"
-        "v_cmp_eq_u32_e64 %[m8], %[lc], %[l8]\n"
-        "v_cmp_eq_u32_e64 %[m9], %[lc], %[l9]\n"
-        "v_cmp_eq_u32_e64 %[m10], %[lc], %[l10]\n"
-        "v_cmp_eq_u32_e64 %[m11], %[lc], %[l11]\n"
-        "v_cmp_eq_u32_e64 %[m12], %[lc], %[l12]\n"
-        "v_cmp_eq_u32_e64 %[m13], %[lc], %[l13]\n"
-        "v_cmp_eq_u32_e64 %[m14], %[lc], %[l14]\n"
-        "v_cmp_eq_u32_e64 %[m15], %[lc], %[l15]\n"
-        "s_mov_b64 %[sv], exec\n"
-        "s_mov_b64 exec, %[m0]\n"
-        "v_add_f64 %[sum], %[sum], %[d0]\n"
-        "s_mov_b64 exec, %[m1]\n"
-        "v_add_f64 %[sum], %[sum], %[d1]\n"
-        "s_mov_b64 exec, %[m2]\n"
-        "v_add_f64 %[sum], %[sum], %[d2]\n"
-        "s_mov_b64 exec, %[m3]\n"
-        "v_add_f64 %[sum], %[sum], %[d3]\n"
-        "s_mov_b64 exec, %[m4]\n"
-        "v_add_f64 %[sum], %[sum], %[d4]\n"
-        "s_mov_b64 exec, %[m5]\n"
-        "v_add_f64 %[sum], %[sum], %[d5]\n"
-        "s_mov_b64 exec, %[m6]\n"
-        "v_add_f64 %[sum], %[sum], %[d6]\n"
-        "s_mov_b64 exec, %[m7]\n"
-        "v_add_f64 %[sum], %[sum], %[d7]\n"
-        "s_mov_b64 exec, %[m8]\n"
-        "v_add_f64 %[sum], %[sum], %[d8]\n"
-        "s_mov_b64 exec, %[m9]\n"
-        "v_add_f64 %[sum], %[sum], %[d9]\n"
-        "s_mov_b64 exec, %[m10]\n"
-        "v_add_f64 %[sum], %[sum], %[d10]\n"
-        "s_mov_b64 exec, %[m11]\n"
-        "v_add_f64 %[sum], %[sum], %[d11]\n"
-        "s_mov_b64 exec, %[m12]\n"
-        "v_add_f64 %[sum], %[sum], %[d12]\n"
-        "s_mov_b64 exec, %[m13]\n"
-        "v_add_f64 %[sum], %[sum], %[d13]\n"
-        "s_mov_b64 exec, %[m14]\n"
-        "v_add_f64 %[sum], %[sum], %[d14]\n"
-        "s_mov_b64 exec, %[m15]\n"
-        "v_add_f64 %[sum], %[sum], %[d15]\n"
-        "s_mov_b64 exec, %[sv]\n"
-        : [sum] "+v"(sum), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [m8] "=&s"(m[8]), [m9] "=&s"(m[9]), [m10] "=&s"(m[10]), [m11] "=&s"(m[11]), [m12] "=&s"(m[12]), [m13] "=&s"(m[13]), [m14] "=&s"(m[14]), [m15] "=&s"(m[15]), [sv] "=&s"(sv)
-        : [lc] "v"(lc), [l0] "v"(li[0]), [l1] "v"(li[1]), [l2] "v"(li[2]), [l3] "v"(li[3]), [l4] "v"(li[4]), [l5] "v"(li[5]), [l6] "v"(li[6]), [l7] "v"(li[7]), [l8] "v"(li[8]), [l9] "v"(li[9]), [l10] "v"(li[10]), [l11] "v"(li[11]), [l12] "v"(li[12]), [l13] "v"(li[13]), [l14] "v"(li[14]), [l15] "v"(li[15]), [d0] "v"(d[0]), [d1] "v"(d[1]), [d2] "v"(d[2]), [d3] "v"(d[3]), [d4] "v"(d[4]), [d5] "v"(d[5]), [d6] "v"(d[6]), [d7] "v"(d[7]), [d8] "v"(d[8]), [d9] "v"(d[9]), [d10] "v"(d[10]), [d11] "v"(d[11]), [d12] "v"(d[12]), [d13] "v"(d[13]), [d14] "v"(d[14]), [d15] "v"(d[15]));
-}
-
 template <int T, int LANES, typename Acc>
 __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int64_t nt,
                                   int64_t n_tiles, int64_t tiles_per_chunk,
@@ -554,6 +435,12 @@ void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const i
     }
 }
 } // namespace
+
+void launch_reduce_partials(const double *partial, int64_t runs, int64_t stride, int64_t m,
+                            double *out, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_reduce_few, dim3((unsigned)m), dim3(256), 0, s, partial, runs, stride, out);
+}
 
 void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
                    int32_t k, const double *w, double *partial, double *out, hipStream_t s) {

@@ -189,7 +189,7 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
             double *out, const void *tiles, int32_t *err_flag, bool timed, double *sT_part,
-            double *sT, bool staged) {
+            double *sT, bool staged, const PrepassRecheck *samples) {
     hipStream_t s = tls.stream;
     int rc;
     if (!staged) launch_fill_u8(L.bad, P, 0, s);
@@ -212,7 +212,7 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
         if ((rc = check_launch("label staging"))) return rc;
     }
     if (!tiles) {
-        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT);
+        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT, samples);
         if ((rc = check_launch("mfma prepass"))) return rc;
         tiles = L.tiles;
     }
@@ -295,6 +295,7 @@ void carve_head(Carver &c, int64_t n, int64_t R, int32_t k, TestHead &h) {
     h.vals = (double *)c.take((size_t)R * sizeof(double));
     h.band = (double *)c.take(sizeof(double));
     h.result = (double *)c.take(4 * sizeof(double));
+    h.rcp = (double *)c.take((size_t)prepass_blocks(n) * kRecheckRows * sizeof(double));
 }
 
 int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t k,
@@ -310,7 +311,7 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked_out,
-                bool sT_ready, const uint16_t *lab16, int64_t stride16) {
+                bool sT_ready, const uint16_t *lab16, int64_t stride16, bool samples_ready) {
     hipStream_t s = tls.stream;
     int rc;
     const int64_t R = n_perms + 1;
@@ -336,7 +337,7 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
                 launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s);
         };
         launch_iota(h.list, S, s);
-        recheck(S);
+        if (!samples_ready) recheck(S);
         if ((rc = check_launch("FP64 recheck"))) return rc;
         launch_tie_band(h.sw, h.vals, S, kBandMargin, h.band, s);
         launch_scatter(h.vals, h.list, S, h.sw, s);
@@ -607,13 +608,25 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         }
     }
     if (!staged && (rc = prepare_test(h, n, grouping, k, n_perms, seed, max_label))) return rc;
-    // the MFMA forms' pre-pass also leaves s_T
+    // The MFMA forms' pre-pass also leaves s_T and the FP64 s_W of the
+    // observed grouping and the first permutations (the recheck's samples).
+    const bool mf = is_mfma(path);
+    PrepassRecheck prc;
+    if (mf) {
+        prc.lab = L.lab;
+        prc.stride = L.mp.n_pad;
+        prc.m = (int32_t)((n_perms < kBandSamples ? n_perms : kBandSamples) + 1);
+        prc.w = h.w;
+        prc.k = k;
+        prc.part = h.rcp;
+        prc.out = h.vals;
+    }
     if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags, true,
-                      h.sTp, h.sT, staged)))
+                      h.sTp, h.sT, staged, mf ? &prc : nullptr)))
         return rc;
     int64_t rechecked = 0;
-    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head + swb, fpb, &rechecked,
-                          is_mfma(path), staged ? L.lab : nullptr, L.mp.n_pad)))
+    if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head + swb, fpb, &rechecked, mf,
+                          staged ? L.lab : nullptr, L.mp.n_pad, mf)))
         return rc;
     if (n_rechecked) *n_rechecked = rechecked;
     return PSTAT_OK;

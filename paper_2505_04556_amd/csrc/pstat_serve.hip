@@ -253,8 +253,17 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     } else {
         launch_stage_labels_pm(L.head.allg, n, R, L.mp.n_pad, L.mp.P_pad, n_groups, L.lab, L.bad,
                                tls.flags, s);
-        // the pre-pass also leaves s_T, as in the whole-test entry point
-        launch_mfma_prepass(mat, n, 2, L.tiles, s, L.head.sTp, L.head.sT);
+        // the pre-pass also leaves s_T and the recheck samples' FP64 s_W, as
+        // in the whole-test entry point
+        PrepassRecheck prc;
+        prc.lab = L.lab;
+        prc.stride = L.mp.n_pad;
+        prc.m = (int32_t)((n_perms < kBandSamples ? n_perms : kBandSamples) + 1);
+        prc.w = L.head.w;
+        prc.k = n_groups;
+        prc.part = L.head.rcp;
+        prc.out = L.head.vals;
+        launch_mfma_prepass(mat, n, 2, L.tiles, s, L.head.sTp, L.head.sT, &prc);
         launch_item_table(L.mp, L.tab, s);
         d.tiles = L.tiles;
         d.lab_pm = L.lab;
@@ -381,7 +390,7 @@ int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all
     int64_t rechecked = 0;
     if ((rc = finish_test(J.head, J.mat, J.n, J.k, J.n_perms,
                           J.kind == 0 ? PSTAT_PATH_PLAIN_F32 : PSTAT_PATH_MFMA_SPLIT_BF16, ws, region,
-                          &rechecked, J.kind != 0)))
+                          &rechecked, J.kind != 0, nullptr, 0, J.kind != 0)))
         return rc;
     if (sW_all)
         HIP_TRY(hipMemcpyAsync(sW_all, J.head.sw, (size_t)R * sizeof(double),

@@ -126,7 +126,8 @@ struct KernelTimer {
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
             double *out, const void *tiles, int32_t *err_flag, bool timed = true,
-            double *sT_part = nullptr, double *sT = nullptr, bool staged = false);
+            double *sT_part = nullptr, double *sT = nullptr, bool staged = false,
+            const PrepassRecheck *samples = nullptr);
 int scan_labels_sync(const int32_t *g, int64_t count, int32_t limit, int32_t *max_label);
 
 // ---- the whole permutation test in phases ------------------------------------
@@ -144,6 +145,8 @@ struct TestHead {
     double *vals;      // [R] recheck values
     double *band;      // tie band
     double *result;    // [4] F_obs, p, s_W_obs, s_T
+    double *rcp;       // [prepass_blocks(n)][kRecheckRows] partials of the
+                       // pre-pass's FP64 recheck of the first rows
 };
 void carve_head(Carver &c, int64_t n, int64_t R, int32_t k, TestHead &h);
 // Observed grouping into row 0, n_perms shuffles after it, weights.
@@ -154,10 +157,13 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 // scratch of at least few_partial_bytes(n, R) bytes.
 // sT_ready: s_T was already left in h.sT (by the pre-pass of the MFMA forms).
 // lab16: the groupings as staged u16 rows of stride16 entries (else h.allg);
-// region must not overlap them.
+// region must not overlap them.  samples_ready: the FP64 s_W of the observed
+// grouping and the first kBandSamples permutations is already in h.vals (the
+// MFMA pre-pass computed it).
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked,
-                bool sT_ready = false, const uint16_t *lab16 = nullptr, int64_t stride16 = 0);
+                bool sT_ready = false, const uint16_t *lab16 = nullptr, int64_t stride16 = 0,
+                bool samples_ready = false);
 
 // Tie band of the p-value recheck: kBandMargin times the largest relative
 // error of the fast path over the observed grouping and the first
