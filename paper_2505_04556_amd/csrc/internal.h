@@ -152,7 +152,9 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
 // out[p] = sum_chunk partial[chunk][p] (fixed order); NaN where bad_perm[p].
 void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, int64_t P,
                          const uint8_t *bad_perm, double *out, hipStream_t s);
-// out[p] = sum_g w[g] * sum_item z[item][p][g] (FP64, fixed order).
+// out[p] = sum_g w[g] * sum_item z[item][p][g] (FP64, fixed order); tmp holds
+// reduce_tmp_doubles(items, P, k) doubles.
+size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k);
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
                         const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s);
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,

@@ -28,24 +28,42 @@ __global__ void k_reduce_plain(const double *__restrict__ partial, int64_t chunk
     }
 }
 
-// tmp[p][g] = sum over items of z[item][p][g] (FP32 -> FP64) in a fixed
-// order: thread (e, r) of a 64 x 4 block adds items r, r + 4, ... ascending;
-// the four slices are then added in order.
+// tmp[slice][p][g] = sum over the items of slice `blockIdx.y` (items
+// slice * per .. (slice + 1) * per - 1) of z[item][p][g] (FP32 -> FP64) in a
+// fixed order: thread (e, r) of a 64 x 4 block adds the slice's items r, r + 4,
+// ... ascending; the four sums are then added in order.  With one slice this
+// is the whole sum; with several (few columns, many items: large n, few
+// permutations) the slices are added by k_reduce_slices.
 __global__ __launch_bounds__(256) void k_reduce_items(const float *__restrict__ z, int64_t items,
-                                                      int64_t P, int32_t k,
+                                                      int64_t per, int64_t P, int32_t k,
                                                       double *__restrict__ tmp) {
     __shared__ double part[4][64];
     const int64_t total = P * k;
     const int el = threadIdx.x % 64, r = threadIdx.x / 64;
     const int64_t e = (int64_t)blockIdx.x * 64 + el;
+    const int64_t i0 = (int64_t)blockIdx.y * per;
+    const int64_t i1 = i0 + per < items ? i0 + per : items;
     double s = 0.0;
     if (e < total) {
 #pragma unroll 4
-        for (int64_t it = r; it < items; it += 4) s += (double)z[it * total + e];
+        for (int64_t it = i0 + r; it < i1; it += 4) s += (double)z[it * total + e];
     }
     part[r][el] = s;
     __syncthreads();
-    if (r == 0 && e < total) tmp[e] = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
+    if (r == 0 && e < total)
+        tmp[(int64_t)blockIdx.y * total + e] =
+            ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
+}
+
+// tmp[p][g] = sum over slices ascending of tmp[1 + slice][p][g] (the slices
+// sit after the first P * k entries).
+__global__ void k_reduce_slices(double *__restrict__ tmp, int64_t total, int64_t slices) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t q = 0; q < slices; q++) s += tmp[(1 + q) * total + e];
+        tmp[e] = s;
+    }
 }
 
 // out[p] = sum over g ascending of w[g] * tmp[p][g].
@@ -153,11 +171,36 @@ void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, i
                        P_pad, P, bad_perm, out);
 }
 
+// Item slices of the MFMA reduction: enough column blocks x slices to fill
+// the chip (about 2,048 work-groups), at least 16 items per slice, at most 64
+// slices; a function of the shape only, so every caller sums in the same order.
+int64_t reduce_slices(int64_t items, int64_t P, int32_t k) {
+    const int64_t cols = ceil_div(P * k, 64);
+    int64_t sl = ceil_div(2048, cols > 0 ? cols : 1);
+    if (sl > items / 16) sl = items / 16;
+    if (sl > 64) sl = 64;
+    return sl > 1 ? sl : 1;
+}
+
+size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k) {
+    const int64_t sl = reduce_slices(items, P, k);
+    return (size_t)(P > 0 ? P : 1) * k * (sl > 1 ? 1 + sl : 1);
+}
+
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
                         const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s) {
     if (P <= 0) return;
-    hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(P * k, 64)), dim3(256), 0, s, z,
-                       items, P, k, tmp);
+    const int64_t total = P * k;
+    const int64_t sl = reduce_slices(items, P, k);
+    if (sl == 1) {
+        hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(total, 64), 1), dim3(256), 0, s,
+                           z, items, items, P, k, tmp);
+    } else {
+        hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(total, 64), (unsigned)sl),
+                           dim3(256), 0, s, z, items, ceil_div(items, sl), P, k, tmp + total);
+        hipLaunchKernelGGL(k_reduce_slices, dim3(blocks_for(total, 256)), dim3(256), 0, s, tmp,
+                           total, sl);
+    }
     hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
                        bad_perm, out);
 }

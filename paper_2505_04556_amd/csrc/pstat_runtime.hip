@@ -169,7 +169,7 @@ void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_ti
     if (own_tiles) L.tiles = c.take(mfma_tile_bytes(n, mfma_dtype(path)));
     L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
     L.z = (float *)c.take((size_t)L.mp.items * (P > 0 ? P : 1) * k * sizeof(float));
-    L.tmp = (double *)c.take((size_t)(P > 0 ? P : 1) * k * sizeof(double));
+    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, P, k) * sizeof(double));
 }
 
 size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {

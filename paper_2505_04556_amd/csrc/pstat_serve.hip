@@ -89,7 +89,7 @@ void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, int kind, JobL
     L.tiles = c.take(mfma_tile_bytes(n, 2));
     L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
     L.z = (float *)c.take((size_t)L.mp.items * R * k * sizeof(float));
-    L.tmp = (double *)c.take((size_t)R * k * sizeof(double));
+    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, R, k) * sizeof(double));
 }
 
 int job_kind(int path, int64_t n, int32_t k) {
