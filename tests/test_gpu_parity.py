@@ -374,3 +374,27 @@ def test_permanova_label_widths(ps, path, n, k, P):
         assert np.isnan(res[1]) and np.isnan(ref["p"])   # no permutations: p undefined
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+
+
+# The observed grouping and the first 15 permutations are recomputed in FP64
+# (inside the pre-pass on the MFMA forms, by the recheck kernel on the plain
+# ones) and written back into sW_all: those entries match the oracle to FP64
+# rounding, not just to the form's tolerance.
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_bf16"])
+@pytest.mark.parametrize("n,sizes,P", [(1000, [100, 200, 300, 400], 999), (700, [300, 400], 9),
+                                       (2100, [500, 600, 1000], 40)])
+def test_fp64_samples_exact(ps, path, n, sizes, P):
+    import torch
+    D = synth.uniform_matrix(n, 77 + n)
+    base = synth.base_labels(sizes)
+    seed = 515 + P
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    ps.pstat_permanova(Dd, bd, len(sizes), P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    sw = sw.cpu().numpy()
+    S = min(P, 15) + 1
+    exact = np.concatenate([[ref["sW_obs"]], ref["sW_perm"][:S - 1]])
+    assert max_rel(sw[:S], exact) <= 1e-12
