@@ -191,6 +191,8 @@ class Server:
     hbm_budget: int
     max_jobs: int = 64
     round_work: float = 1.5e11      # pair-permutations per round (~20 ms of plain kernel)
+    # a request that has waited this long for memory is passed by no later one
+    aging_s: float = 0.5
     max_units: int = 8192
     keep_sW: bool = False
     clock: Callable[[], float] = time.perf_counter
@@ -219,7 +221,8 @@ class Server:
                 pending.append(reqs[nxt])
                 nxt += 1
             # admission: oldest first; later ones may pass a request that waits
-            # for memory (first fit)
+            # for memory (first fit) until it has waited aging_s, after which
+            # admission stops at it (no starvation of large requests)
             for req in list(pending):
                 fp = self.executor.footprint(req)
                 if fp > self.hbm_budget:
@@ -227,6 +230,8 @@ class Server:
                     out[req.id].error = f"footprint {fp} exceeds the budget {self.hbm_budget}"
                     continue
                 if len(active) >= self.max_jobs or used + fp > self.hbm_budget:
+                    if realtime and t - req.arrival >= self.aging_s:
+                        break
                     continue
                 try:
                     handle, n_units, unit_cost = self.executor.create(req)

@@ -86,7 +86,7 @@ def run(reqs, budget, **kw):
     clock = Clock()
     ex = FakeExecutor(clock, **{k: v for k, v in kw.items() if k in ("rate", "fail_ids")})
     srv = Server(ex, hbm_budget=budget, clock=clock, sleep=clock.sleep, round_work=2e9,
-                 **{k: v for k, v in kw.items() if k in ("max_jobs", "max_units")})
+                 **{k: v for k, v in kw.items() if k in ("max_jobs", "max_units", "aging_s")})
     return srv.run(reqs), ex
 
 
@@ -164,3 +164,30 @@ def test_autotune_keys_and_cache(tmp_path):
     autotune.save_cache({"a": {"x": 1}}, f)
     assert autotune.load_cache(f) == {"a": {"x": 1}}
     assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+def test_aging_stops_small_requests_from_starving_a_large_one():
+    # Small requests, each running 0.3 s and arriving every 0.2 s, overlap in
+    # pairs; a large one (arriving at 0.5 s) fits only when no small job is
+    # resident.  If later requests could always pass it, a new small job would
+    # be admitted before the previous one ends and the large one would wait
+    # for the whole stream.  Once it has waited aging_s, admission stops at
+    # it, the resident small jobs drain and it runs.
+    def reqs():
+        out = [Request(id=i, n=1000, k=2, grouping=np.zeros(1000, np.int32), n_perms=5999,
+                       seed=i, arrival=0.2 * i) for i in range(40)]
+        out.append(Request(id=40, n=5000, k=3, grouping=np.zeros(5000, np.int32), n_perms=999,
+                           seed=40, arrival=0.5))
+        return out
+    ex0 = FakeExecutor(Clock())
+    small, large = ex0.footprint(reqs()[0]), ex0.footprint(reqs()[40])
+    budget = large + int(0.9 * small)          # two small jobs fit, large only alone
+    assert 2 * small <= budget < large + small
+    res_no, _ = run(reqs(), budget, rate=1e10, aging_s=1e9)
+    res_ag, _ = run(reqs(), budget, rate=1e10, aging_s=0.5)
+    for res in (res_no, res_ag):
+        assert res["stats"]["completed"] == 41
+    last_small = max(res_no["outcomes"][i].admitted for i in range(40))
+    assert res_no["outcomes"][40].admitted >= last_small       # starved behind the stream
+    # aged at 1.0 s; the two resident small jobs end within 0.6 s
+    assert res_ag["outcomes"][40].admitted <= 0.5 + 0.5 + 0.6 + 0.05
