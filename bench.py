@@ -281,8 +281,8 @@ def main() -> int:
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the permutation "
-              "axis would shard across GPUs, but this build measures one GPU's share.",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the permutation "
+              "axis would shard across GPUs, and this benchmark measures one GPU's share.",
               file=sys.stderr)
         return 2
 

@@ -31,8 +31,9 @@ def ps(dev):
 
 
 def record(name, payload):
-    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(d):
+    # the tables also go to $PSTAT_RESULTS_DIR when it names a directory
+    d = os.environ.get("PSTAT_RESULTS_DIR", "")
+    if d and os.path.isdir(d):
         with open(os.path.join(d, f"fullsize_{name}.json"), "w") as f:
             json.dump(payload, f, indent=1)
     print(name, json.dumps(payload), flush=True)

@@ -320,8 +320,8 @@ def test_precision_table_n1000(ps):
                            mean_rel_sW=float(np.mean(np.abs(got - ref) / ref)))
         assert max_rel(got, ref) <= TOL[path], (path, table[path])
     ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("PSTAT_RESULTS_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "precision_n1000.json"), "w") as f:
             json.dump(table, f, indent=1)
     print("n1000", json.dumps(table), flush=True)
