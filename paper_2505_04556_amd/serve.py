@@ -94,6 +94,7 @@ class GpuExecutor(Executor):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.Stream(self.device)     # default priority
         self.max_units = max_units
+        self.max_jobs = max_jobs         # job slots of the device server
         with torch.cuda.stream(self.stream):
             self.server = ps.pstat_serve_create(max_jobs, max_units)
         self.live = {}
@@ -212,6 +213,8 @@ class Server:
         rounds = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
+        # no more resident jobs than the executor has slots for
+        max_jobs = min(self.max_jobs, getattr(self.executor, "max_jobs", self.max_jobs))
         if not realtime:
             for r in reqs:
                 out[r.id].arrival = 0.0
@@ -229,7 +232,7 @@ class Server:
                     pending.remove(req)
                     out[req.id].error = f"footprint {fp} exceeds the budget {self.hbm_budget}"
                     continue
-                if len(active) >= self.max_jobs or used + fp > self.hbm_budget:
+                if len(active) >= max_jobs or used + fp > self.hbm_budget:
                     if realtime and t - req.arrival >= self.aging_s:
                         break
                     continue

@@ -102,3 +102,42 @@ def test_executor_warmup_leaves_nothing_behind(ps):
         assert res["stats"]["completed"] == 3
     finally:
         ex.close()
+
+
+@pytest.mark.slow
+def test_serving_trace_matches_oracle_on_a_subset(ps):
+    """The 64-request serving trace (n in 1k..20k, k in 2..12, 999 or 9,999
+    permutations), served with all arrivals at once under an 8 GB budget on the
+    library's own choice of form; every request with n <= 2,000 (the ones the
+    FP64 oracle finishes in about a second) is checked against the oracle:
+    s_W of every permutation within 1e-5, F_obs within 1e-5, p identical.
+    Every request must complete."""
+    import synth.device as sd
+    from paper_2505_04556_amd.serve import GpuExecutor, Request, Server
+    specs = synth.serving_requests(64, 4.0, 4000)
+    reqs = [Request(id=t["id"], n=t["n"], k=t["k"], grouping=synth.base_labels(t["sizes"]),
+                    n_perms=t["n_perms"], seed=t["perm_seed"], arrival=t["arrival"],
+                    make_matrix=(lambda dev, n=t["n"], s=t["matrix_seed"]:
+                                 sd.uniform_matrix(n, s, dev)))
+            for t in specs]
+    ex = GpuExecutor(max_jobs=32, max_units=8192, path="auto")
+    try:
+        srv = Server(ex, hbm_budget=8 << 30, keep_sW=True, round_work=1.5e11, max_units=8192)
+        res = srv.run(reqs, realtime=False)
+    finally:
+        ex.close()
+    errors = {i: o.error for i, o in res["outcomes"].items() if o.error}
+    assert not errors, errors
+    assert res["stats"]["completed"] == 64
+    checked = 0
+    for t in specs:
+        if t["n"] > 2000:
+            continue
+        o = res["outcomes"][t["id"]]
+        ref = oracle.permanova(synth.uniform_matrix(t["n"], t["matrix_seed"]),
+                               synth.base_labels(t["sizes"]), t["n_perms"], t["perm_seed"])
+        assert max_rel(o.sW_all[1:], ref["sW_perm"]) <= 1e-5, t["id"]
+        assert abs(o.result[0] - ref["F_obs"]) <= 1e-5 * abs(ref["F_obs"]), t["id"]
+        assert o.result[1] == ref["p"], t["id"]
+        checked += 1
+    assert checked >= 16

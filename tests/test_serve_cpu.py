@@ -191,3 +191,29 @@ def test_aging_stops_small_requests_from_starving_a_large_one():
     assert res_no["outcomes"][40].admitted >= last_small       # starved behind the stream
     # aged at 1.0 s; the two resident small jobs end within 0.6 s
     assert res_ag["outcomes"][40].admitted <= 0.5 + 0.5 + 0.6 + 0.05
+
+
+def test_admission_respects_the_executors_job_slots():
+    # all requests at once; the executor has 5 job slots, the server allows more
+    reqs = trace(30, seed=6)
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    ex.max_jobs = 5
+    live = []
+    orig = ex.create
+
+    def create(req):
+        live.append(req.id)
+        assert len(live) - len(done) <= 5, "more resident jobs than slots"
+        return orig(req)
+    done = []
+    orig_release = ex.release
+
+    def release(h):
+        done.append(h)
+        orig_release(h)
+    ex.create, ex.release = create, release
+    srv = Server(ex, hbm_budget=1 << 40, clock=clock, sleep=clock.sleep, round_work=2e9,
+                 max_jobs=64)
+    res = srv.run(reqs, realtime=False)
+    assert res["stats"]["completed"] == 30
