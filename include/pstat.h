@@ -150,9 +150,11 @@ int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed
 /* The whole permutation test on one matrix, all on the device:
  * weights 1/n_g from `grouping` (n_groups groups), n_perms shuffles
  * (pstat_permute with `seed`), s_W of the observed grouping and of every
- * shuffle, s_T, F and p.  Permutations whose s_W lies within the path's error
- * band of the observed value are recomputed with PSTAT_PATH_PLAIN_F64 before
- * counting; this SYNCHRONISES the stream once.  result (device, 4 doubles) =
+ * shuffle, s_T, F and p.  The observed grouping, the first 15 shuffles and
+ * every shuffle whose s_W lies within the path's error band of the observed
+ * value are recomputed in FP64 before counting; the call SYNCHRONISES the
+ * stream twice (label check, count of near ties).  F counts the non-empty
+ * groups among the n_groups labels.  result (device, 4 doubles) =
  * {F_obs, p, s_W_obs, s_T}; sW_all (device, n_perms + 1 doubles, may be NULL)
  * receives s_W of the observed grouping then of each shuffle; n_rechecked
  * (host, may be NULL) receives how many permutations were recomputed. */

@@ -171,8 +171,10 @@ void launch_tie_band(const double *fast, const double *exact, int64_t S, double 
 void launch_iota(int32_t *list, int64_t m, hipStream_t s);
 void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *sW_all,
                     hipStream_t s);
+// result = [F_obs, p, s_W_obs, s_T]; with counts (group sizes, [k]) F counts
+// only the non-empty groups.
 void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32_t k,
-                        const double *p, double *result, hipStream_t s);
+                        const uint32_t *counts, const double *p, double *result, hipStream_t s);
 
 // ---- permutation generator (k_permute.hip) -----------------------------------
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,

@@ -151,11 +151,21 @@ __global__ void k_scatter(const double *__restrict__ vals, const int32_t *__rest
         sW_all[list[i]] = vals[i];
 }
 
+// result = [F_obs, p, s_W_obs, s_T]; F takes k as the number of non-empty
+// groups of counts[0 .. k) when counts is given (one wave counts them).
 __global__ void k_pack_result(const double *__restrict__ sW_all, const double *__restrict__ sT,
-                              int64_t n, int32_t k, const double *__restrict__ p,
-                              double *__restrict__ result) {
+                              int64_t n, int32_t k, const uint32_t *__restrict__ counts,
+                              const double *__restrict__ p, double *__restrict__ result) {
+    int32_t kk = k;
+    if (counts) {
+        int32_t c = 0;
+        for (int32_t g = threadIdx.x; g < k; g += 64) c += counts[g] ? 1 : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+        kk = c;
+    }
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        result[0] = pseudo_F(sW_all[0], *sT, n, k);
+        result[0] = pseudo_F(sW_all[0], *sT, n, kk);
         result[1] = *p;
         result[2] = sW_all[0];
         result[3] = *sT;
@@ -240,8 +250,9 @@ void launch_scatter(const double *vals, const int32_t *list, int64_t m, double *
 }
 
 void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32_t k,
-                        const double *p, double *result, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_result, dim3(1), dim3(64), 0, s, sW_all, sT, n, k, p, result);
+                        const uint32_t *counts, const double *p, double *result, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_result, dim3(1), dim3(64), 0, s, sW_all, sT, n, k, counts, p,
+                       result);
 }
 
 } // namespace pstat

@@ -360,7 +360,7 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
         rechecked = S - 1 + m;
     }
     launch_pvalue(h.sw, h.sw + 1, n_perms, h.pv, s);
-    launch_pack_result(h.sw, h.sT, n, k, h.pv, h.result, s);
+    launch_pack_result(h.sw, h.sT, n, k, h.counts, h.pv, h.result, s);
     if ((rc = check_launch("result"))) return rc;
     if (rechecked_out) *rechecked_out = rechecked;
     return PSTAT_OK;

@@ -398,3 +398,24 @@ def test_fp64_samples_exact(ps, path, n, sizes, P):
     S = min(P, 15) + 1
     exact = np.concatenate([[ref["sW_obs"]], ref["sW_perm"][:S - 1]])
     assert max_rel(sw[:S], exact) <= 1e-12
+
+
+# An empty group among the n_groups labels: it gets weight 0 and F counts only
+# the non-empty groups, as the oracle does.
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16"])
+def test_permanova_with_an_empty_group(ps, path):
+    import torch
+    n, P, seed = 800, 199, 31
+    base = synth.base_labels([200, 0, 250, 350])      # label 1 unused
+    D = synth.uniform_matrix(n, 808)
+    ref = oracle.permanova(D, base, P, seed)
+    assert ref["k"] == 3
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, _ = ps.pstat_permanova(Dd, bd, 4, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+    assert res[1] == ref["p"]
