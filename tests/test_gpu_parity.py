@@ -419,3 +419,27 @@ def test_permanova_with_an_empty_group(ps, path):
     assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert res[1] == ref["p"]
+
+
+# Tiny and ragged whole tests on every form (n around one 128-row panel and
+# one 64-column block, n not a multiple of 4, fewer permutations than the 15
+# samples).
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("n,sizes,P", [(3, [1, 2], 5), (5, [2, 3], 40), (66, [30, 36], 17),
+                                       (131, [40, 41, 50], 63), (257, [100, 157], 8)])
+def test_permanova_tiny_and_ragged(ps, path, n, sizes, P):
+    import torch
+    D = synth.uniform_matrix(n, 900 + n)
+    base = synth.base_labels(sizes)
+    seed = 77 + n
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, _ = ps.pstat_permanova(Dd, bd, len(sizes), P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+    assert res[1] == ref["p"]
+    assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
