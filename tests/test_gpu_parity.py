@@ -443,3 +443,41 @@ def test_permanova_tiny_and_ragged(ps, path, n, sizes, P):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert res[1] == ref["p"]
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+
+
+# The library keeps its state (stream, workspace, flags, form) per host
+# thread: two threads running whole tests on their own streams at once get
+# exactly what each gets alone.
+def test_two_threads_on_their_own_streams(ps):
+    import threading
+    import torch
+    cases = [(900, [300, 600], 255, 41, "mfma_split_bf16"), (1100, [200, 400, 500], 127, 42, "plain_f32")]
+    inputs = []
+    for n, sizes, P, seed, path in cases:
+        D = synth.uniform_matrix(n, 3000 + n)
+        inputs.append((to_dev(D, synth.base_labels(sizes)), len(sizes), P, seed, path))
+
+    def one(i, out):
+        (Dd, bd), k, P, seed, path = inputs[i]
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ps.pstat_set_path(path)
+            sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                res, _ = ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+            st.synchronize()
+            out[i] = (res.cpu().numpy(), sw.cpu().numpy())
+
+    alone = {}
+    for i in range(2):
+        one(i, alone)
+    both = {}
+    ts = [threading.Thread(target=one, args=(i, both)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    ps.pstat_set_path("auto")
+    for i in range(2):
+        assert np.array_equal(alone[i][0], both[i][0])
+        assert np.array_equal(alone[i][1], both[i][1])
