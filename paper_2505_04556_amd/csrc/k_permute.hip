@@ -28,6 +28,8 @@
 //
 // Fallbacks: one lane per permutation with the arrays in LDS, or in place in
 // the output when not even one array fits.
+#include <atomic>
+
 #include "internal.h"
 
 namespace pstat {
@@ -479,6 +481,24 @@ __global__ __launch_bounds__(64) void k_permute_global(const int32_t *__restrict
     shuffle<int32_t>(a, n, seed, p);
 }
 
+// Raises a kernel's dynamic-LDS limit to `limit` (the device's maximum) the
+// first time it is launched on a device, instead of before every launch.
+template <typename K>
+void allow_lds(K *kernel, size_t limit) {
+    constexpr int kDevices = 64;
+    static std::atomic<size_t> set[kDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) {
+        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)limit);
+        return;
+    }
+    if (set[dev].load(std::memory_order_relaxed) == limit) return;
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)limit);
+    set[dev].store(limit, std::memory_order_relaxed);
+}
+
 template <typename E>
 int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t *out,
                size_t lds_limit, hipStream_t s) {
@@ -488,8 +508,7 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
     if (ppw > 64) ppw = 64;
     if (ppw > P) ppw = P;
     const size_t bytes = (size_t)ppw * row;
-    (void)hipFuncSetAttribute((const void *)k_permute_lds<E>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    allow_lds(k_permute_lds<E>, lds_limit);
     const int64_t blocks = ceil_div(P, ppw);
     const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0) && ((uintptr_t)out % 16 == 0);
     hipLaunchKernelGGL(k_permute_lds<E>, dim3((unsigned)blocks), dim3(64), bytes, s, base, n, P,
@@ -534,8 +553,7 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
     const dim3 grid((unsigned)blocks), block((unsigned)(64 * waves));
 #define PSTAT_BATCH_CASE(B_)                                                                     \
     if (B == B_) {                                                                               \
-        (void)hipFuncSetAttribute((const void *)k_permute_batch<S, B_, O>,                       \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);       \
+        allow_lds(k_permute_batch<S, B_, O>, lds_limit);                                         \
         hipLaunchKernelGGL((k_permute_batch<S, B_, O>), grid, block, bytes, s, base, n, P, seed,  \
                            pw, vec, out, ostride, ovec);                                         \
         return 0;                                                                                \
