@@ -363,14 +363,14 @@ def main() -> int:
             got = r["sW"][1:1 + m]
             acc[path] = float(np.max(np.abs(got - cpu["sW"]) / np.abs(cpu["sW"])))
 
-    ok_paths = [p for p in runs if p in ("plain_f32", "mfma_split_bf16")]
+    ok_paths = [p for p in runs if p in ("plain_f32", "mfma_split_bf16", "mfma_split3_bf16")]
     best = min(ok_paths, key=lambda p: runs[p]["ms_per_step"])
     r = runs[best]
     value = pair_perms / (r["ms_per_step"] / 1e3) / 1e9
     kern_ms = r["kernel_ms_total"] / max(1, r["kernel_launches"])
     R = P + 1
     if best.startswith("mfma"):
-        s = 2 if "split" in best else 1
+        s = 3 if "split3" in best else 2 if "split" in best else 1
         work = 2.0 * k * s * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12
         traffic = None
@@ -381,7 +381,7 @@ def main() -> int:
                     unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
                     traffic_unit="HBM bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, "
                                  "calibrated on a 1 GiB copy)",
-                    kernel="k_mfma<2> (split-BF16)", kernel_ms=round(kern_ms, 4),
+                    kernel=f"k_mfma<{s}> ({best})", kernel_ms=round(kern_ms, 4),
                     work_per_launch=f"{2 * k * s} flop x {pairs} pairs x {R} groupings")
     else:
         work = PLAIN_OPS_PER_PAIRPERM * pairs * R
@@ -407,7 +407,9 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 hi+lo -> f32 accumulate -> f64" if best.startswith("mfma") else "f32 -> f64",
+        "dtype": ("bf16 hi+mid+lo -> f32 accumulate -> f64" if best == "mfma_split3_bf16"
+                  else "bf16 hi+lo -> f32 accumulate -> f64" if best.startswith("mfma")
+                  else "f32 -> f64"),
         "data": "synthetic (seeded Euclidean distances of N(0,1) points, 32 dims, scaled to [0,1])",
         "config": {"workload": cfg["name"], "n": n, "k": k, "group_sizes": cfg["sizes"],
                    "n_perms": P, "path": best},

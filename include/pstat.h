@@ -56,7 +56,10 @@ extern "C" {
 #define PSTAT_PATH_MFMA_F16 2          /* MFMA, D^2 in FP16                */
 #define PSTAT_PATH_MFMA_SPLIT_BF16 3   /* MFMA, D^2 as BF16 hi + BF16 lo   */
 #define PSTAT_PATH_PLAIN_F64 4         /* VALU kernel, FP64 throughout     */
-#define PSTAT_N_PATHS 5
+#define PSTAT_PATH_MFMA_SPLIT3_BF16 5  /* MFMA, D^2 as BF16 hi + mid + lo:
+                                          every FP32 square represented
+                                          exactly (1.5x the split cost)  */
+#define PSTAT_N_PATHS 6
 
 /* ---- context ------------------------------------------------------------ */
 

@@ -35,12 +35,14 @@ PSTAT_PATH_MFMA_BF16 = 1
 PSTAT_PATH_MFMA_F16 = 2
 PSTAT_PATH_MFMA_SPLIT_BF16 = 3
 PSTAT_PATH_PLAIN_F64 = 4
+PSTAT_PATH_MFMA_SPLIT3_BF16 = 5
 PATH_NAMES = {
     PSTAT_PATH_PLAIN_F32: "plain_f32",
     PSTAT_PATH_MFMA_BF16: "mfma_bf16",
     PSTAT_PATH_MFMA_F16: "mfma_f16",
     PSTAT_PATH_MFMA_SPLIT_BF16: "mfma_split_bf16",
     PSTAT_PATH_PLAIN_F64: "plain_f64",
+    PSTAT_PATH_MFMA_SPLIT3_BF16: "mfma_split3_bf16",
 }
 PATH_IDS = {v: k for k, v in PATH_NAMES.items()}
 PATH_IDS["auto"] = PSTAT_PATH_AUTO

@@ -120,6 +120,22 @@ struct MfmaPlan {
 MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, int ncols,
                    int n_cu);
 size_t mfma_tile_bytes(int64_t n, int dtype);
+// FP16 form: the squares are multiplied by 2^e, a power of two chosen from the
+// largest |d| of the strict upper triangle so that the largest square lands
+// in [2^14, 2^15) (FP16 is finite below 65,504 and has full precision above
+// 2^-14: scaling keeps big inputs finite and small ones normal); the FP64
+// reduction multiplies by 2^-e.  Both are exact.  The bits of that largest
+// |d| sit in a 32-bit cell after the FP16 tiles (f16_max_cell).
+const uint32_t *f16_max_cell(const void *tiles, int64_t n);
+__device__ inline int f16_scale_exp(uint32_t maxabs_bits) {
+    const float d = __builtin_bit_cast(float, maxabs_bits);
+    const float m = d * d;   // the same FP32 product as each square
+    if (!(m > 0.0f) || !__builtin_isfinite(m)) return 0;
+    int E = 0;
+    (void)frexpf(m, &E);     // m < 2^E
+    const int e = 15 - E;
+    return e < -126 ? -126 : e > 127 ? 127 : e;
+}
 // Pre-pass: strict-upper d^2 of 128-row panels into MFMA fragment order.
 // FP64 s_W of rows 0 .. m-1 (m <= kRecheckRows) of a staged u16 label table
 // (rows of `stride` entries), computed inside the MFMA pre-pass; part holds
@@ -155,8 +171,10 @@ void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, i
 // out[p] = sum_g w[g] * sum_item z[item][p][g] (FP64, fixed order); tmp holds
 // reduce_tmp_doubles(items, P, k) doubles.
 size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k);
+// f16max: the FP16 form's scale cell (f16_max_cell), NULL for the other forms.
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
-                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s);
+                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s,
+                        const uint32_t *f16max = nullptr);
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,
               double *F, hipStream_t s);
 void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,

@@ -5,7 +5,9 @@
 //     s_W[p] = sum_g w_g (G_p^T U G_p)_gg,
 // which is exactly Algorithm 1's sum (section 2) regrouped: (G^T U G)_gg adds
 // u_ij over the pairs i < j that both carry label g.  G is 0/1, so it is exact
-// in any input type; only U is rounded (to BF16, FP16, or BF16 hi + BF16 lo).
+// in any input type; only U is rounded (to BF16, FP16, or BF16 hi + BF16 lo),
+// or split without rounding into BF16 hi + mid + lo: an FP32 square has 24
+// significant bits and each BF16 part takes 8 of them (below).
 //
 // Blocking.  Rows are cut into 128-row panels and columns into 64-column K
 // blocks.  A pre-pass writes, for each panel I, its K blocks from the diagonal
@@ -92,8 +94,12 @@ template <int DT, bool RC>
 __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, int64_t n,
                                                  int64_t kb_total, int64_t comp_units, int vec,
                                                  uint4 *__restrict__ tiles,
-                                                 double *__restrict__ sT_part, PrepassRecheck rc) {
+                                                 double *__restrict__ sT_part, PrepassRecheck rc,
+                                                 const uint32_t *__restrict__ f16max) {
     constexpr int Q = RC ? kRecheckRows : 1;
+    // FP16: the power of two that brings the largest square into [2^14, 2^15)
+    float f16sc = 1.0f;
+    if constexpr (DT == 1) f16sc = ldexpf(1.0f, f16_scale_exp(*f16max));
     __shared__ float sm[kPanel][kKBlock + 1];
     __shared__ double sred[4];
     // recheck labels: rows as [grouping][row % 16][row / 16] (a thread's 8
@@ -204,24 +210,35 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
             const int rb = idx / 256, s = (idx / 64) % 4, lane = idx % 64;
             const int r = rb * 32 + (lane % 32);
             const int cb = 32 * (lane / 32) + 8 * s;
-            uint32_t hw[4], lw[4];
+            uint32_t hw[4], lw[4], tw[4];
             for (int e2 = 0; e2 < 4; e2++) {
                 const float x0 = sm[r][cb + 2 * e2], x1 = sm[r][cb + 2 * e2 + 1];
                 if (DT == 1) {
-                    hw[e2] = (uint32_t)to_f16_bits(x0) | ((uint32_t)to_f16_bits(x1) << 16);
+                    hw[e2] = (uint32_t)to_f16_bits(x0 * f16sc) |
+                             ((uint32_t)to_f16_bits(x1 * f16sc) << 16);
                 } else {
                     const uint16_t h0 = to_bf16_bits(x0), h1 = to_bf16_bits(x1);
                     hw[e2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-                    if (DT == 2) {
-                        const uint16_t l0 = to_bf16_bits(x0 - bf16_bits_to_float(h0));
-                        const uint16_t l1 = to_bf16_bits(x1 - bf16_bits_to_float(h1));
-                        lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                    // x - hi is exact in FP32 (hi is x rounded to 8 bits, so
+                    // they share the exponent range); for DT 3 the remainder
+                    // is split once more and the last remainder, at most 8
+                    // significant bits, is exact in BF16 (normal range)
+                    const float r0 = x0 - bf16_bits_to_float(h0);
+                    const float r1 = x1 - bf16_bits_to_float(h1);
+                    const uint16_t l0 = to_bf16_bits(r0), l1 = to_bf16_bits(r1);
+                    lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                    if (DT == 3) {
+                        const uint16_t t0 = to_bf16_bits(r0 - bf16_bits_to_float(l0));
+                        const uint16_t t1 = to_bf16_bits(r1 - bf16_bits_to_float(l1));
+                        tw[e2] = (uint32_t)t0 | ((uint32_t)t1 << 16);
                     }
                 }
             }
             tiles[off * kUnitU4 + idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            if (DT == 2)
+            if (DT >= 2)
                 tiles[(comp_units + off) * kUnitU4 + idx] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            if (DT == 3)
+                tiles[(2 * comp_units + off) * kUnitU4 + idx] = make_uint4(tw[0], tw[1], tw[2], tw[3]);
         }
     }
     if (sT_part) {
@@ -243,6 +260,34 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
         if (tid < Q)
             rc.part[(int64_t)blockIdx.x * Q + tid] =
                 ((rred[0][tid] + rred[1][tid]) + rred[2][tid]) + rred[3][tid];
+    }
+}
+
+// Largest |d| over the strict upper triangle, as float bits (non-negative
+// floats order like their bit patterns; a NaN orders above infinity), folded
+// into *cell with one atomicMax per work-group.  Work-group b takes rows b,
+// b + gridDim.x, ...
+__global__ __launch_bounds__(256) void k_max_abs_upper(const float *__restrict__ mat, int64_t n,
+                                                       uint32_t *__restrict__ cell) {
+    __shared__ uint32_t red[4];
+    uint32_t m = 0;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+        for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
+            const uint32_t b = __builtin_bit_cast(uint32_t, mat[(uint64_t)i * (uint64_t)n + j]) &
+                               0x7FFFFFFFu;
+            m = b > m ? b : m;
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t v = (uint32_t)__shfl_xor((int)m, o);
+        m = v > m ? v : m;
+    }
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t r = red[0];
+        for (int q = 1; q < 4; q++) r = red[q] > r ? red[q] : r;
+        atomicMax(cell, r);
     }
 }
 
@@ -296,7 +341,8 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// DT: 0 bf16, 1 f16, 2 split bf16 (hi and lo MFMAs into one accumulator).
+// DT: 0 bf16, 1 f16, 2 split bf16 (hi and lo MFMAs into one accumulator),
+// 3 three-part split bf16 (hi, mid, lo).
 // NF: 32-column fragments per wave; a work-group of 4 waves covers 128 rows x
 // (4 * NF * 32) columns.
 //
@@ -318,7 +364,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     const int32_t *__restrict__ tab, int64_t item, int64_t nb, const uint16_t *__restrict__ lab,
     int64_t n_pad, int32_t k, int64_t P, float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
-    constexpr int NC = DT == 2 ? 2 : 1;     // A components (hi, lo)
+    constexpr int NC = DT == 3 ? 3 : DT == 2 ? 2 : 1;   // A components (hi, [mid,] lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
     constexpr int COLS = 4 * NF * 32;       // columns per work-group
     // Labels of one K block: per permutation 8 chunks of 8 u16 (16 bytes) and
@@ -539,6 +585,12 @@ __global__ __launch_bounds__(256) void k_mfma(
 // touch ((COLS - 1) / k + 2, 9 slots each, 256 per round), rounded up to the
 // instantiated counts.
 constexpr int kLqBins[4] = {2, 4, 7, 10};
+// Static LDS of k_mfma<DT, NF, LQ>: two buffers of A (one 16 KB block per
+// component) and two of labels; gfx950 gives a work-group 160 KB.
+constexpr bool mfma_lds_fits(int dt, int nf, int lq) {
+    (void)nf;
+    return 2 * (dt == 3 ? 3 : dt == 2 ? 2 : 1) * kUnitU4 * 16 + 2 * lq * 256 * 16 <= 160 * 1024;
+}
 int lq_bin(int cols, int32_t k) {
     const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 9, 256);
     for (int b : kLqBins)
@@ -566,7 +618,13 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
 size_t mfma_tile_bytes(int64_t n, int dtype) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t units = panels * (panels + 1);
-    return (size_t)units * kUnitU4 * 16 * (dtype == 2 ? 2 : 1);
+    // FP16: one 256-byte slot after the tiles for the scale cell
+    return (size_t)units * kUnitU4 * 16 * (dtype == 3 ? 3 : dtype == 2 ? 2 : 1) +
+           (dtype == 1 ? 256 : 0);
+}
+
+const uint32_t *f16_max_cell(const void *tiles, int64_t n) {
+    return (const uint32_t *)((const char *)tiles + mfma_tile_bytes(n, 1) - 256);
 }
 
 MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, int ncols,
@@ -587,6 +645,9 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     for (int64_t I = 0; I < pl.panels; I++) items += ceil_div(pl.kb_total - 2 * I, kc);
     pl.items = items;
     pl.ncols = (ncols == 256) ? 256 : 512;
+    // three A components and the labels of 512 columns of two groups do not
+    // fit in LDS together: 256 columns then
+    if (dtype == 3 && pl.ncols == 512 && !mfma_lds_fits(3, 4, lq_bin(512, k))) pl.ncols = 256;
     pl.N = (int64_t)k * P;
     pl.nblocks = ceil_div(pl.N > 0 ? pl.N : 1, pl.ncols);
     pl.P_pad = ceil_div(pl.nblocks * pl.ncols, k);
@@ -608,16 +669,25 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     const dim3 grid((unsigned)blocks);
     uint4 *t = (uint4 *)tiles;
     const PrepassRecheck none{};
+    uint32_t *cell = nullptr;
+    if (dtype == 1) {
+        cell = const_cast<uint32_t *>(f16_max_cell(tiles, n));
+        launch_fill_i32((int32_t *)cell, 1, 0, s);
+        const int64_t mb = n < 2048 ? n : 2048;
+        hipLaunchKernelGGL(k_max_abs_upper, dim3((unsigned)mb), dim3(256), 0, s, mat, n, cell);
+    }
 #define PSTAT_PREPASS(DT_, RC_)                                                                   \
     hipLaunchKernelGGL((k_prepass<DT_, RC_>), grid, dim3(256), 0, s, mat, n, kb_total, comp_units, \
-                       vec, t, sT_part, rc ? *rc : none)
+                       vec, t, sT_part, rc ? *rc : none, cell)
     if (rc) {
         if (dtype == 0) PSTAT_PREPASS(0, true);
         else if (dtype == 1) PSTAT_PREPASS(1, true);
+        else if (dtype == 3) PSTAT_PREPASS(3, true);
         else PSTAT_PREPASS(2, true);
     } else {
         if (dtype == 0) PSTAT_PREPASS(0, false);
         else if (dtype == 1) PSTAT_PREPASS(1, false);
+        else if (dtype == 3) PSTAT_PREPASS(3, false);
         else PSTAT_PREPASS(2, false);
     }
 #undef PSTAT_PREPASS
@@ -648,7 +718,12 @@ int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const
     case 2: launch_mfma_t<DT, NF, 2>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
     case 4: launch_mfma_t<DT, NF, 4>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
     case 7: launch_mfma_t<DT, NF, 7>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
-    case 10: launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+    case 10:
+        if constexpr (mfma_lds_fits(DT, NF, 10)) {
+            launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s);
+            return 0;
+        }
+        return -1;
     }
     return -1;
 }
@@ -673,6 +748,7 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
     PSTAT_MFMA_CASE(0)
     PSTAT_MFMA_CASE(1)
     PSTAT_MFMA_CASE(2)
+    PSTAT_MFMA_CASE(3)
 #undef PSTAT_MFMA_CASE
     return -1;
 }

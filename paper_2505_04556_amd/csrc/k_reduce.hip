@@ -66,15 +66,18 @@ __global__ void k_reduce_slices(double *__restrict__ tmp, int64_t total, int64_t
     }
 }
 
-// out[p] = sum over g ascending of w[g] * tmp[p][g].
+// out[p] = sum over g ascending of w[g] * tmp[p][g]; with f16max set, times
+// 2^-e, undoing the FP16 form's power-of-two scaling of the squares.
 __global__ void k_weight_groups(const double *__restrict__ tmp, int64_t P, int32_t k,
                                 const double *__restrict__ w,
-                                const uint8_t *__restrict__ bad_perm, double *__restrict__ out) {
+                                const uint8_t *__restrict__ bad_perm, double *__restrict__ out,
+                                const uint32_t *__restrict__ f16max) {
+    const double unscale = f16max ? ldexp(1.0, -f16_scale_exp(*f16max)) : 1.0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
          p += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int32_t g = 0; g < k; g++) s += w[g] * tmp[p * k + g];
-        out[p] = (bad_perm && bad_perm[p]) ? NAN : s;
+        out[p] = (bad_perm && bad_perm[p]) ? NAN : s * unscale;
     }
 }
 
@@ -198,7 +201,8 @@ size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k) {
 }
 
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
-                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s) {
+                        const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s,
+                        const uint32_t *f16max) {
     if (P <= 0) return;
     const int64_t total = P * k;
     const int64_t sl = reduce_slices(items, P, k);
@@ -212,7 +216,7 @@ void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, con
                            total, sl);
     }
     hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
-                       bad_perm, out);
+                       bad_perm, out, f16max);
 }
 
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,

@@ -115,10 +115,11 @@ int acquire_workspace(size_t bytes, char **out) {
 
 bool is_mfma(int path) {
     return path == PSTAT_PATH_MFMA_BF16 || path == PSTAT_PATH_MFMA_F16 ||
-           path == PSTAT_PATH_MFMA_SPLIT_BF16;
+           path == PSTAT_PATH_MFMA_SPLIT_BF16 || path == PSTAT_PATH_MFMA_SPLIT3_BF16;
 }
 int mfma_dtype(int path) {
-    return path == PSTAT_PATH_MFMA_BF16 ? 0 : path == PSTAT_PATH_MFMA_F16 ? 1 : 2;
+    return path == PSTAT_PATH_MFMA_BF16 ? 0 : path == PSTAT_PATH_MFMA_F16 ? 1
+         : path == PSTAT_PATH_MFMA_SPLIT3_BF16 ? 3 : 2;
 }
 
 // Default form for a shape when the thread asked for PSTAT_PATH_AUTO (the
@@ -221,7 +222,8 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
         return fail(PSTAT_EINVAL, "no MFMA kernel for %d columns", L.mp.ncols);
     timer.stop(s);
     if ((rc = check_launch("mfma s_W"))) return rc;
-    launch_reduce_mfma(L.z, L.mp.items, P, k, w, L.bad, L.tmp, out, s);
+    launch_reduce_mfma(L.z, L.mp.items, P, k, w, L.bad, L.tmp, out, s,
+                       L.mp.dtype == 1 ? f16_max_cell(tiles, n) : nullptr);
     return check_launch("mfma reduce");
 }
 
@@ -413,7 +415,7 @@ int pstat_set_stream(void *hip_stream) {
 }
 
 int pstat_resolve_path(int path, int64_t n, int32_t n_groups) {
-    if (path < PSTAT_PATH_AUTO || path > PSTAT_PATH_PLAIN_F64)
+    if (path < PSTAT_PATH_AUTO || path >= PSTAT_N_PATHS)
         return fail(PSTAT_EINVAL, "unknown path %d", path);
     return resolve_path(path, n, n_groups);
 }

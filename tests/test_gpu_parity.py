@@ -15,7 +15,7 @@ from gpu_util import TOL, load_pstat, max_rel, problem, to_dev
 
 pytestmark = pytest.mark.gpu
 
-ALL_PATHS = ["plain_f32", "plain_f64", "mfma_split_bf16", "mfma_f16", "mfma_bf16"]
+ALL_PATHS = ["plain_f32", "plain_f64", "mfma_split_bf16", "mfma_split3_bf16", "mfma_f16", "mfma_bf16"]
 
 
 @pytest.fixture(scope="module")
@@ -102,7 +102,7 @@ def test_plain_tunings(ps, tile, lanes):
     assert max_rel(got, ref) <= TOL["plain_f32"]
 
 
-@pytest.mark.parametrize("path", ["mfma_split_bf16", "mfma_f16", "mfma_bf16"])
+@pytest.mark.parametrize("path", ["mfma_split_bf16", "mfma_split3_bf16", "mfma_f16", "mfma_bf16"])
 @pytest.mark.parametrize("kcols,ncols", [(64, 256), (128, 512), (512, 256), (0, 512)])
 def test_mfma_tunings(ps, path, kcols, ncols):
     D, base, perms, w = problem(700, [100, 250, 350], 50, mseed=6, pseed=7)
@@ -131,6 +131,45 @@ def test_dyadic_inputs_bit_exact(ps, path):
     ref = oracle.sW(D, perms, w)
     got = run_sW(ps, path, D, perms, w)
     assert np.array_equal(got, ref), f"{path}: max rel err {max_rel(got, ref):.3e}"
+
+
+@pytest.mark.parametrize("kcols", [0, 128])
+def test_split3_carries_24_bit_squares_exactly(ps, kcols):
+    # Squares with 24 significant bits (odd m^2 / 2^24, m = 4095, 4093): BF16
+    # hi + lo keeps 16 of them, hi + mid + lo all.  One non-zero pair per
+    # (panel, K chunk) work item, so no FP32 sum ever adds two of them; group
+    # sizes of 128 make the weights exact.  The three-part form must match
+    # the oracle bit for bit, the two-part one cannot.
+    n = 256
+    D = np.zeros((n, n), dtype=np.float32)
+    for i, j, m in ((3, 200, 4095), (150, 250, 4093)):
+        D[i, j] = D[j, i] = np.float32(m / 4096)
+    base = synth.base_labels([128, 128])
+    perms = np.vstack([base, oracle.permute(base, 63, 21)])
+    w = synth.inv_group_sizes([128, 128])
+    ref = oracle.sW(D, perms, w)
+    assert np.count_nonzero(ref) > 10
+    got = run_sW(ps, "mfma_split3_bf16", D, perms, w, tuning=(kcols, 0))
+    assert np.array_equal(got, ref), f"max rel err {max_rel(got, ref):.3e}"
+    two = run_sW(ps, "mfma_split_bf16", D, perms, w)
+    assert not np.array_equal(two, ref)
+    assert max_rel(two, ref) <= 2.0 ** -16
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("scale", [1e3, 3e-4, 2.0 ** 50, 0.0])
+def test_distance_range(ps, path, scale):
+    # Squares far outside FP16's range: up to 1e6 (FP16 overflows past
+    # 65,504), about 1e-9 (FP16 flushes below 6e-8), 2^100; the FP16 form
+    # scales them by a power of two first.  An all-zero matrix gives zeros.
+    D, base, perms, w = problem(300, [100, 200], 40, mseed=31, pseed=32)
+    D = (D.astype(np.float64) * scale).astype(np.float32)
+    ref = oracle.sW(D, perms, w)
+    got = run_sW(ps, path, D, perms, w)
+    if scale == 0.0:
+        assert np.all(got == 0.0)
+    else:
+        assert max_rel(got, ref) <= TOL[path], f"{path} x{scale}: {max_rel(got, ref):.3e}"
 
 
 @pytest.mark.parametrize("path", ALL_PATHS)
@@ -313,7 +352,8 @@ def test_precision_table_n1000(ps):
     ref = oracle.sW(D, rows, w)
     Dd, gd, wd = to_dev(D, rows, w)
     table = {}
-    for path in ("plain_f64", "plain_f32", "mfma_split_bf16", "mfma_f16", "mfma_bf16"):
+    for path in ("plain_f64", "plain_f32", "mfma_split_bf16", "mfma_split3_bf16", "mfma_f16",
+                 "mfma_bf16"):
         ps.pstat_set_path(path)
         got = ps.pstat_sW_k(Dd, gd, k, wd).cpu().numpy()
         table[path] = dict(max_rel_sW=max_rel(got, ref),
@@ -327,7 +367,7 @@ def test_precision_table_n1000(ps):
     print("n1000", json.dumps(table), flush=True)
 
 
-@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_bf16"])
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_split3_bf16", "mfma_bf16"])
 def test_permanova_matches_oracle(ps, path):
     import torch
     cfg = synth.config(0)
