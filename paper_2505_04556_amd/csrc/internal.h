@@ -116,9 +116,12 @@ struct MfmaPlan {
     int64_t nblocks;  // ceil(N / ncols)
     int64_t P_pad;    // permutation rows of the staged label table
     size_t tile_bytes;// bytes of the pre-squared tile storage (all components)
+    bool cx;          // complement form: one group (the largest) gets no columns
+    int32_t kcol;     // columns per grouping: k, or k - 1 in the complement form
 };
+// cx asks for the complement form (taken when its label staging fits in LDS).
 MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, int ncols,
-                   int n_cu);
+                   int n_cu, bool cx = false);
 size_t mfma_tile_bytes(int64_t n, int dtype);
 // FP16 form: the squares are multiplied by 2^e, a power of two chosen from the
 // largest |d| of the strict upper triangle so that the largest square lands
@@ -151,18 +154,45 @@ struct PrepassRecheck {
     double *out = nullptr;
 };
 // Pre-squares the strict upper triangle into MFMA fragment order; with
-// sT_part (sT_partials_count(n) doubles) set it also leaves s_T in *sT, and
-// with rc the FP64 s_W of rc->m staged label rows in rc->out.
+// sT_part (sT_partials_count(n) doubles) set it also leaves s_T in *sT, with
+// rc the FP64 s_W of rc->m staged label rows in rc->out, and with rcs
+// (complement_part_doubles(n)) the FP64 row and column sums of each unit's
+// stored values.
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
                          double *sT_part = nullptr, double *sT = nullptr,
-                         const PrepassRecheck *rc = nullptr);
+                         const PrepassRecheck *rc = nullptr, double *rcs = nullptr);
 int64_t prepass_blocks(int64_t n);
 size_t mfma_table_bytes(const MfmaPlan &pl);
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);
 // z[item][P][k] FP32 sums of the (G^T U G) diagonal per (panel, K chunk) item;
-// tab is scratch for the item table (mfma_table_bytes).
+// tab is scratch for the item table (mfma_table_bytes).  Complement form
+// (pl.cx): z[item][P][k - 1][2], per column the rows of its group and the
+// rows not in group *Lp.
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
-                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s);
+                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s,
+                const int32_t *Lp = nullptr);
+
+// ---- complement form (k_reduce.hip) ------------------------------------------
+// Device state of one complement-form evaluation.
+struct Complement {
+    int32_t *L = nullptr;     // [1] the group without columns (the largest)
+    double *rcs = nullptr;    // complement_part_doubles(n): per-unit row/column sums
+    double *slices = nullptr; // complement_slice_doubles(n): partial sums of rcs
+    double *v = nullptr;      // [n_pad] row + column sums of the stored U
+    double *r = nullptr;      // [n_pad] row sums
+    double *S = nullptr;      // [1] sum of the stored U
+    double *vnot = nullptr;   // [P] sum of v over the objects not in L, per grouping
+};
+int64_t complement_part_doubles(int64_t n);
+int64_t complement_slice_doubles(int64_t n);
+// *L = the lowest index of the largest count
+void launch_largest_group(const uint32_t *counts, int32_t k, int32_t *L, hipStream_t s);
+// v, r and S from the pre-pass's per-unit sums.
+void launch_complement_sums(const Complement &cx, int64_t n, hipStream_t s);
+// vnot[p] = sum over i < n with lab[p * stride + i] != *L of v[i], p < P
+// (stride a multiple of 128, rows padded with a label other than *L).
+void launch_vnot(const Complement &cx, const uint16_t *lab, int64_t stride, int64_t n, int64_t P,
+                 hipStream_t s);
 
 // ---- reductions (k_reduce.hip) ---------------------------------------------
 // out[p] = sum_chunk partial[chunk][p] (fixed order); NaN where bad_perm[p].
@@ -171,10 +201,12 @@ void launch_reduce_plain(const double *partial, int64_t chunks, int64_t P_pad, i
 // out[p] = sum_g w[g] * sum_item z[item][p][g] (FP64, fixed order); tmp holds
 // reduce_tmp_doubles(items, P, k) doubles.
 size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k);
-// f16max: the FP16 form's scale cell (f16_max_cell), NULL for the other forms.
+// f16max: the FP16 form's scale cell (f16_max_cell), NULL for the other forms;
+// cx: the complement form's state (z then holds k - 1 column pairs per
+// grouping, and tmp reduce_tmp_doubles(items, P, 2 (k - 1)) doubles).
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
                         const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s,
-                        const uint32_t *f16max = nullptr);
+                        const uint32_t *f16max = nullptr, const Complement *cx = nullptr);
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,
               double *F, hipStream_t s);
 void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,

@@ -22,6 +22,18 @@
 // Each (panel, K chunk) work item writes its own z; they are summed in FP64 and
 // weighted by w_g in FP64 afterwards, so FP32 only ever accumulates one K
 // chunk.
+//
+// Complement form (the whole test, where every grouping has the same group
+// sizes).  One group L (the largest) gets no columns: with e_L = 1 - sum of
+// the other one-hot columns,
+//     e_L^T U e_L = S - sum_{i: g(i) != L} v_i + sum_{g != L} N_g,
+// where S is the sum of U, v_i its row plus column sums, and
+// N_g = sum_{i: g(i) != L} (U e_g)_i, which the epilogue gets next to the
+// diagonal term at no extra MFMA cost.  k - 1 columns per grouping instead
+// of k.  S and v are FP64 sums of the values the MFMAs see (the rounded
+// squares), so the identity holds for them exactly; only the FP32
+// accumulation error of the N_g is scaled up, by (n - n_L)^2 / (n n_L)
+// relative to s_W.
 #include <hip/hip_bf16.h>
 
 #include "internal.h"
@@ -90,12 +102,37 @@ __device__ inline int64_t unit_panel(int64_t unit, int64_t kb_total) {
 // the column's (masked adds, rows in order), times the column label's weight,
 // into one running FP64 sum per grouping; the sums are reduced like s_T and
 // written as one partial per work-group and grouping.
+//
+// With rcs set (the complement form) each unit also leaves the FP64 sums of
+// its 128 rows and 64 columns of the stored values -- hi + lo, hi + mid + lo,
+// the BF16 value, or the scaled FP16 value, each exact in FP32 -- at
+// rcs[unit * 192 + row] and rcs[unit * 192 + 128 + column], in a fixed order.
+// The writer loop leaves those values in LDS; they are summed after the next
+// unit's loads are issued (or after the last unit).
+__device__ inline void unit_sums(const float (*sm)[kKBlock + 1], double *__restrict__ out,
+                                 int tid) {
+    // rows: two threads per row, 32 columns each, then their sum
+    const int rr = tid >> 1, rh = tid & 1;
+    double a = 0.0;
+    for (int c = 0; c < 32; c++) a += (double)sm[rr][rh * 32 + c];
+    a += __shfl_xor(a, 1);
+    if (rh == 0) out[rr] = a;
+    // columns: four threads per column, 32 rows each, then in pairs
+    const int cc = tid >> 2, c4 = tid & 3;
+    double b = 0.0;
+    for (int r = 0; r < 32; r++) b += (double)sm[c4 * 32 + r][cc];
+    b += __shfl_xor(b, 1);
+    b += __shfl_xor(b, 2);
+    if (c4 == 0) out[128 + cc] = b;
+}
+
 template <int DT, bool RC>
 __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, int64_t n,
                                                  int64_t kb_total, int64_t comp_units, int vec,
                                                  uint4 *__restrict__ tiles,
                                                  double *__restrict__ sT_part, PrepassRecheck rc,
-                                                 const uint32_t *__restrict__ f16max) {
+                                                 const uint32_t *__restrict__ f16max,
+                                                 double *__restrict__ rcs) {
     constexpr int Q = RC ? kRecheckRows : 1;
     // FP16: the power of two that brings the largest square into [2^14, 2^15)
     float f16sc = 1.0f;
@@ -115,6 +152,7 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
     double acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) acc[q] = 0.0;
+    int64_t prev = -1;   // the unit whose stored values LDS holds
     for (int64_t unit = blockIdx.x; unit < comp_units; unit += gridDim.x) {
         const int64_t I = unit_panel(unit, kb_total);
         const int64_t kb = 2 * I + (unit - I * (kb_total - I + 1));
@@ -146,6 +184,11 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
             if (tid < 128 && qc < rc.m)
                 lc = *reinterpret_cast<const uint4 *>(rc.lab + qc * rc.stride + c0 + (tid % 8) * 8);
         }
+        if (rcs && prev >= 0) {
+            __syncthreads();   // the previous unit's stored values are in LDS
+            unit_sums(sm, rcs + prev * 192, tid);
+        }
+        prev = unit;
         __syncthreads();   // the previous unit's LDS reads are done
         // squares: FP32 into LDS for the fragments; exact FP64 for s_T and
         // the recheck (0 off the strict upper triangle)
@@ -213,9 +256,12 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
             uint32_t hw[4], lw[4], tw[4];
             for (int e2 = 0; e2 < 4; e2++) {
                 const float x0 = sm[r][cb + 2 * e2], x1 = sm[r][cb + 2 * e2 + 1];
+                float s0, s1;   // the values the MFMAs will see
                 if (DT == 1) {
-                    hw[e2] = (uint32_t)to_f16_bits(x0 * f16sc) |
-                             ((uint32_t)to_f16_bits(x1 * f16sc) << 16);
+                    const uint16_t h0 = to_f16_bits(x0 * f16sc), h1 = to_f16_bits(x1 * f16sc);
+                    hw[e2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                    s0 = (float)__builtin_bit_cast(_Float16, h0);
+                    s1 = (float)__builtin_bit_cast(_Float16, h1);
                 } else {
                     const uint16_t h0 = to_bf16_bits(x0), h1 = to_bf16_bits(x1);
                     hw[e2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
@@ -227,12 +273,23 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                     const float r1 = x1 - bf16_bits_to_float(h1);
                     const uint16_t l0 = to_bf16_bits(r0), l1 = to_bf16_bits(r1);
                     lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                    s0 = bf16_bits_to_float(h0);
+                    s1 = bf16_bits_to_float(h1);
+                    if (DT >= 2) {   // hi + lo has at most 24 significant bits
+                        s0 += bf16_bits_to_float(l0);
+                        s1 += bf16_bits_to_float(l1);
+                    }
                     if (DT == 3) {
                         const uint16_t t0 = to_bf16_bits(r0 - bf16_bits_to_float(l0));
                         const uint16_t t1 = to_bf16_bits(r1 - bf16_bits_to_float(l1));
                         tw[e2] = (uint32_t)t0 | ((uint32_t)t1 << 16);
+                        s0 += bf16_bits_to_float(t0);
+                        s1 += bf16_bits_to_float(t1);
                     }
                 }
+                // each element is read and rewritten by this thread only
+                sm[r][cb + 2 * e2] = s0;
+                sm[r][cb + 2 * e2 + 1] = s1;
             }
             tiles[off * kUnitU4 + idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             if (DT >= 2)
@@ -240,6 +297,10 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
             if (DT == 3)
                 tiles[(2 * comp_units + off) * kUnitU4 + idx] = make_uint4(tw[0], tw[1], tw[2], tw[3]);
         }
+    }
+    if (rcs && prev >= 0) {
+        __syncthreads();
+        unit_sums(sm, rcs + prev * 192, tid);
     }
     if (sT_part) {
 #pragma unroll
@@ -358,11 +419,14 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 // even number of K blocks), so every access names its buffer statically and
 // the compiler can see that reads of one buffer do not depend on the copy into
 // the other.
-template <int DT, int NF, int LQ>
+// CX: complement form -- kcol = k - 1 columns per grouping, for the groups
+// other than L; the epilogue writes two sums per column (rows of the
+// column's group, rows not in L).  Otherwise kcol = k.
+template <int DT, int NF, int LQ, bool CX>
 __device__ __attribute__((always_inline)) inline void mfma_unit(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t item, int64_t nb, const uint16_t *__restrict__ lab,
-    int64_t n_pad, int32_t k, int64_t P, float *__restrict__ z) {
+    int64_t n_pad, int32_t kcol, int32_t Lg, int64_t P, float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
     constexpr int NC = DT == 3 ? 3 : DT == 2 ? 2 : 1;   // A components (hi, [mid,] lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
@@ -382,8 +446,8 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     const int wave = tid / 64, lane = tid % 64;
     const int half = lane / 32, col = lane % 32;
     // permutations of this work-group's columns (p_hi < the padded count)
-    const int64_t p_lo = nb * COLS / k;
-    const int64_t p_hi = (nb * COLS + COLS - 1) / k;
+    const int64_t p_lo = nb * COLS / kcol;
+    const int64_t p_hi = (nb * COLS + COLS - 1) / kcol;
 
     // Per column fragment: its group (both 16-bit halves) and the LDS label
     // slot of its permutation (everything else is derived from these two).
@@ -392,8 +456,9 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
 #pragma unroll
     for (int nf = 0; nf < NF; nf++) {
         const int64_t c = nb * COLS + wave * (NF * 32) + nf * 32 + col;
-        const int64_t p = c / k;
-        const uint32_t g = (uint32_t)(c - p * k);
+        const int64_t p = c / kcol;
+        uint32_t g = (uint32_t)(c - p * kcol);
+        if (CX && g >= (uint32_t)Lg) g++;   // the column's group skips L
         gg[nf] = g | (g << 16);
         // K step s of a block uses rows 8s + 32*half + 0..7: chunk s + 4*half
         lslot[nf] = (int)(p - p_lo) * kLStride + 4 * half;
@@ -550,7 +615,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                 // (rb % 2) * 4 + a of its K block, bytes 8*half .. 8*half + 7
                 l4[rb][a] = L2[(slot0 + (rb % 2) * 4 + a) * 2 + half];
         }
-        float zs = 0.0f;
+        float zs = 0.0f, zn = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
 #pragma unroll
@@ -558,33 +623,46 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                 const uint32_t lab4[4] = {l4[rb][a].x & 0xFFFFu, l4[rb][a].x >> 16,
                                           l4[rb][a].y & 0xFFFFu, l4[rb][a].y >> 16};
 #pragma unroll
-                for (int b = 0; b < 4; b++) zs += (lab4[b] == g) ? acc[rb][nf][4 * a + b] : 0.0f;
+                for (int b = 0; b < 4; b++) {
+                    const float y = acc[rb][nf][4 * a + b];
+                    zs += (lab4[b] == g) ? y : 0.0f;
+                    if (CX) zn += (lab4[b] != (uint32_t)Lg) ? y : 0.0f;
+                }
             }
         }
         zs += __shfl_xor(zs, 32);
         const int64_t p = p_lo + slot0 / kLStride;
-        if (half == 0 && p < P) z[(item * P + p) * k + g] = zs;
+        if (CX) {
+            zn += __shfl_xor(zn, 32);
+            const uint32_t gc = g - (g > (uint32_t)Lg ? 1u : 0u);   // column within p
+            if (half == 0 && p < P)
+                *reinterpret_cast<float2 *>(&z[((item * P + p) * kcol + gc) * 2]) =
+                    make_float2(zs, zn);
+        } else if (half == 0 && p < P) {
+            z[(item * P + p) * kcol + g] = zs;
+        }
     }
 }
 
-template <int DT, int NF, int LQ>
+template <int DT, int NF, int LQ, bool CX>
 __global__ __launch_bounds__(256) void k_mfma(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
-    const uint16_t *__restrict__ lab, int64_t n_pad, int32_t k, int64_t P,
-    float *__restrict__ z) {
+    const uint16_t *__restrict__ lab, int64_t n_pad, int32_t kcol, const int32_t *__restrict__ Lp,
+    int64_t P, float *__restrict__ z) {
     const int64_t gpad = gridDim.x;
     const int64_t bid = blockIdx.x;
     const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
     if (logical >= grid_real) return;
-    mfma_unit<DT, NF, LQ>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
-                          lab, n_pad, k, P, z);
+    const int32_t Lg = CX ? *Lp : 0;
+    mfma_unit<DT, NF, LQ, CX>(tiles, comp_units, kb_total, tab, logical / nblocks,
+                              logical % nblocks, lab, n_pad, kcol, Lg, P, z);
 }
 
 // Label-copy rounds for the permutations that COLS columns of k groups can
 // touch ((COLS - 1) / k + 2, 9 slots each, 256 per round), rounded up to the
 // instantiated counts.
-constexpr int kLqBins[4] = {2, 4, 7, 10};
+constexpr int kLqBins[5] = {2, 4, 5, 7, 10};
 // Static LDS of k_mfma<DT, NF, LQ>: two buffers of A (one 16 KB block per
 // component) and two of labels; gfx950 gives a work-group 160 KB.
 constexpr bool mfma_lds_fits(int dt, int nf, int lq) {
@@ -609,8 +687,8 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
     if (logical >= *count) return;
     const UnitDesc u = units[logical];
     const JobDesc &j = jobs[u.job];
-    mfma_unit<2, 4, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
-                        u.pgroup, j.lab_pm, j.n_pad_m, j.k, j.R, j.z);
+    mfma_unit<2, 4, 10, false>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
+                               u.pgroup, j.lab_pm, j.n_pad_m, j.k, 0, j.R, j.z);
 }
 
 } // namespace
@@ -628,7 +706,7 @@ const uint32_t *f16_max_cell(const void *tiles, int64_t n) {
 }
 
 MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, int ncols,
-                   int n_cu) {
+                   int n_cu, bool cx) {
     (void)n_cu;
     MfmaPlan pl{};
     pl.dtype = dtype;
@@ -645,12 +723,20 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     for (int64_t I = 0; I < pl.panels; I++) items += ceil_div(pl.kb_total - 2 * I, kc);
     pl.items = items;
     pl.ncols = (ncols == 256) ? 256 : 512;
-    // three A components and the labels of 512 columns of two groups do not
-    // fit in LDS together: 256 columns then
-    if (dtype == 3 && pl.ncols == 512 && !mfma_lds_fits(3, 4, lq_bin(512, k))) pl.ncols = 256;
-    pl.N = (int64_t)k * P;
+    // The labels of the permutations a work-group's columns touch must fit in
+    // LDS beside the A blocks: fewer columns per work-group when they do not
+    // (three A components, or one or two columns per permutation), and the
+    // full form when not even 256 columns fit.
+    auto fits = [&](int cols, int32_t kc) {
+        const int lq = lq_bin(cols, kc);
+        return lq > 0 && mfma_lds_fits(dtype, cols / 128, lq);
+    };
+    pl.cx = cx && k >= 2 && (fits(pl.ncols, k - 1) || fits(256, k - 1));
+    pl.kcol = pl.cx ? k - 1 : k;
+    if (!fits(pl.ncols, pl.kcol)) pl.ncols = 256;
+    pl.N = (int64_t)pl.kcol * P;
     pl.nblocks = ceil_div(pl.N > 0 ? pl.N : 1, pl.ncols);
-    pl.P_pad = ceil_div(pl.nblocks * pl.ncols, k);
+    pl.P_pad = ceil_div(pl.nblocks * pl.ncols, pl.kcol);
     if (pl.P_pad < P) pl.P_pad = P;
     pl.tile_bytes = mfma_tile_bytes(n, dtype);
     return pl;
@@ -659,7 +745,7 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
 size_t mfma_table_bytes(const MfmaPlan &pl) { return (size_t)pl.items * 3 * sizeof(int32_t); }
 
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
-                         double *sT_part, double *sT, const PrepassRecheck *rc) {
+                         double *sT_part, double *sT, const PrepassRecheck *rc, double *rcs) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t kb_total = panels * 2;
     const int64_t comp_units = panels * (panels + 1);
@@ -678,7 +764,7 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     }
 #define PSTAT_PREPASS(DT_, RC_)                                                                   \
     hipLaunchKernelGGL((k_prepass<DT_, RC_>), grid, dim3(256), 0, s, mat, n, kb_total, comp_units, \
-                       vec, t, sT_part, rc ? *rc : none, cell)
+                       vec, t, sT_part, rc ? *rc : none, cell, rcs)
     if (rc) {
         if (dtype == 0) PSTAT_PREPASS(0, true);
         else if (dtype == 1) PSTAT_PREPASS(1, true);
@@ -704,23 +790,30 @@ int64_t prepass_blocks(int64_t n) {
 
 template <int DT, int NF, int LQ>
 void launch_mfma_t(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
-                   int64_t grid_real, int64_t gpad, const uint16_t *lab, int32_t k, int64_t P,
-                   float *z, hipStream_t s) {
-    hipLaunchKernelGGL((k_mfma<DT, NF, LQ>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
-                       pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad, k, P, z);
+                   int64_t grid_real, int64_t gpad, const uint16_t *lab, const int32_t *Lp,
+                   int64_t P, float *z, hipStream_t s) {
+    if (pl.cx)
+        hipLaunchKernelGGL((k_mfma<DT, NF, LQ, true>), dim3((unsigned)gpad), dim3(256), 0, s, t,
+                           comp_units, pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad,
+                           pl.kcol, Lp, P, z);
+    else
+        hipLaunchKernelGGL((k_mfma<DT, NF, LQ, false>), dim3((unsigned)gpad), dim3(256), 0, s, t,
+                           comp_units, pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad,
+                           pl.kcol, Lp, P, z);
 }
 
 template <int DT, int NF>
 int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
-                   int64_t grid_real, int64_t gpad, const uint16_t *lab, int32_t k, int64_t P,
-                   float *z, hipStream_t s) {
-    switch (lq_bin(4 * NF * 32, k)) {
-    case 2: launch_mfma_t<DT, NF, 2>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
-    case 4: launch_mfma_t<DT, NF, 4>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
-    case 7: launch_mfma_t<DT, NF, 7>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s); return 0;
+                   int64_t grid_real, int64_t gpad, const uint16_t *lab, const int32_t *Lp,
+                   int64_t P, float *z, hipStream_t s) {
+    switch (lq_bin(4 * NF * 32, pl.kcol)) {
+    case 2: launch_mfma_t<DT, NF, 2>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 4: launch_mfma_t<DT, NF, 4>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 5: launch_mfma_t<DT, NF, 5>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 7: launch_mfma_t<DT, NF, 7>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
     case 10:
         if constexpr (mfma_lds_fits(DT, NF, 10)) {
-            launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, k, P, z, s);
+            launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s);
             return 0;
         }
         return -1;
@@ -729,10 +822,11 @@ int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const
 }
 
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
-                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s) {
+                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s, const int32_t *Lp) {
     (void)n;
     if (pl.ncols != 256 && pl.ncols != 512) return -1;
     if (k < 2 || (pl.kchunk & 1)) return -1;
+    if (pl.cx && (!Lp || pl.kcol != k - 1)) return -1;
     hipLaunchKernelGGL(k_item_table, dim3((unsigned)ceil_div(pl.panels, 256)), dim3(256), 0, s,
                        pl.panels, pl.kb_total, pl.kchunk, tab);
     const int64_t grid_real = pl.items * pl.nblocks;
@@ -742,8 +836,8 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
 #define PSTAT_MFMA_CASE(DT_)                                                                      \
     if (pl.dtype == DT_) {                                                                        \
         if (pl.ncols == 512)                                                                      \
-            return launch_mfma_lq<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s); \
-        return launch_mfma_lq<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, k, P, z, s);     \
+            return launch_mfma_lq<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, s); \
+        return launch_mfma_lq<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, s);     \
     }
     PSTAT_MFMA_CASE(0)
     PSTAT_MFMA_CASE(1)

@@ -426,6 +426,9 @@ void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const i
         else if (mm <= 8)
             hipLaunchKernelGGL((k_sw_few<8, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
                                nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
+        else if (mm <= 12)
+            hipLaunchKernelGGL((k_sw_few<12, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat,
+                               n, nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
         else
             hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
                                dim3(256), 0, s, mat, n, nt, tiles, tpc, g, gstride, rows + b, mm, k,

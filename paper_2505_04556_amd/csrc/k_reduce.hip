@@ -81,6 +81,150 @@ __global__ void k_weight_groups(const double *__restrict__ tmp, int64_t P, int32
     }
 }
 
+// Complement form: column c of grouping p stands for group c (c < L) or
+// c + 1; tmp[p][2c] sums the rows of that group, tmp[p][2c + 1] the rows not
+// in L.  out[p] = sum_c w[g(c)] tmp[p][2c]
+//               + w[L] ((S - vnot[p]) + sum_c tmp[p][2c + 1]),
+// c ascending, then times 2^-e for the FP16 form.
+__global__ void k_weight_cx(const double *__restrict__ tmp, int64_t P, int32_t k,
+                            const double *__restrict__ w, const uint8_t *__restrict__ bad_perm,
+                            double *__restrict__ out, const uint32_t *__restrict__ f16max,
+                            const int32_t *__restrict__ Lp, const double *__restrict__ S,
+                            const double *__restrict__ vnot) {
+    const double unscale = f16max ? ldexp(1.0, -f16_scale_exp(*f16max)) : 1.0;
+    const int32_t L = *Lp, kc = k - 1;
+    const double sum_u = *S;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const double *t = tmp + p * 2 * kc;
+        double diag = 0.0, rest = 0.0;
+        for (int32_t c = 0; c < kc; c++) {
+            diag += w[c < L ? c : c + 1] * t[2 * c];
+            rest += t[2 * c + 1];
+        }
+        const double s = diag + w[L] * ((sum_u - vnot[p]) + rest);
+        out[p] = (bad_perm && bad_perm[p]) ? NAN : s * unscale;
+    }
+}
+
+// *L = lowest index of the largest count (one thread).
+__global__ void k_largest_group(const uint32_t *__restrict__ counts, int32_t k,
+                                int32_t *__restrict__ L) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int32_t b = 0;
+    uint32_t m = counts[0];
+    for (int32_t g = 1; g < k; g++)
+        if (counts[g] > m) {
+            m = counts[g];
+            b = g;
+        }
+    *L = b;
+}
+
+// Row sums r_i and row + column sums v_i of the stored U from the pre-pass's
+// per-unit sums (unit (I, kb) is number I (kb_total - I + 1) + kb - 2I; row
+// i lies in panel i / 128, column i in K block i / 64), in a fixed order:
+// slice y of kComplementSlices takes every kComplementSlices-th unit of the
+// row's panel and of the column's K block into part[y][0][i] and
+// part[y][1][i]; the slices are then added in order.
+constexpr int kComplementSlices = 8;
+__global__ void k_complement_slices(const double *__restrict__ rcs, int64_t n_pad,
+                                    int64_t kb_total, double *__restrict__ part) {
+    const int64_t y = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t I = i / 128, kj = i / 64;
+        double a = 0.0, b = 0.0;
+        for (int64_t kb = 2 * I + y; kb < kb_total; kb += kComplementSlices)
+            a += rcs[(I * (kb_total - I + 1) + kb - 2 * I) * 192 + i % 128];
+        for (int64_t J = y; 2 * J <= kj; J += kComplementSlices)
+            b += rcs[(J * (kb_total - J + 1) + kj - 2 * J) * 192 + 128 + i % 64];
+        part[(y * 2) * n_pad + i] = a;
+        part[(y * 2 + 1) * n_pad + i] = b;
+    }
+}
+
+__global__ void k_complement_sums(const double *__restrict__ part, int64_t n_pad,
+                                  double *__restrict__ v, double *__restrict__ r) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0.0, b = 0.0;
+        for (int y = 0; y < kComplementSlices; y++) {
+            a += part[(y * 2) * n_pad + i];
+            b += part[(y * 2 + 1) * n_pad + i];
+        }
+        r[i] = a;
+        v[i] = a + b;
+    }
+}
+
+// Fixed-order sum of `count` doubles by one work-group: thread t adds
+// t, t + 256, ... ascending, then a butterfly per wave and the four waves in
+// order.
+__device__ inline double block_sum_fixed(double a, double *red4) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+    if (threadIdx.x % 64 == 0) red4[threadIdx.x / 64] = a;
+    __syncthreads();
+    const double t = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_sum_fixed(const double *__restrict__ x, int64_t count,
+                                                   double *__restrict__ out) {
+    __shared__ double red[4];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) a += x[i];
+    const double t = block_sum_fixed(a, red);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// vnot[p] = sum over i with lab[p][i] != *L of v[i]: kVnotRows groupings per
+// work-group (each v entry is read once for all of them), eight labels (16
+// bytes) per thread and step, fixed order.  Rows are read to their padded
+// length (a multiple of 128): the pad entries' v is zero.
+constexpr int kVnotRows = 8;
+__global__ __launch_bounds__(256) void k_vnot(const uint16_t *__restrict__ lab, int64_t stride,
+                                              int64_t n_pad, int64_t P,
+                                              const int32_t *__restrict__ Lp,
+                                              const double *__restrict__ v,
+                                              double *__restrict__ vnot) {
+    __shared__ double red[4][kVnotRows];
+    const uint32_t L = (uint32_t)*Lp;
+    for (int64_t p0 = (int64_t)blockIdx.x * kVnotRows; p0 < P;
+         p0 += (int64_t)gridDim.x * kVnotRows) {
+        double a[kVnotRows];
+#pragma unroll
+        for (int q = 0; q < kVnotRows; q++) a[q] = 0.0;
+        for (int64_t c = threadIdx.x; c < n_pad / 8; c += 256) {
+            const double2 *vv = reinterpret_cast<const double2 *>(v + c * 8);
+            const double2 v0 = vv[0], v1 = vv[1], v2 = vv[2], v3 = vv[3];
+            const double x[8] = {v0.x, v0.y, v1.x, v1.y, v2.x, v2.y, v3.x, v3.y};
+#pragma unroll
+            for (int q = 0; q < kVnotRows; q++) {
+                if (p0 + q >= P) break;
+                const uint4 l = reinterpret_cast<const uint4 *>(lab + (p0 + q) * stride)[c];
+                const uint32_t lw[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+                for (int e = 0; e < 8; e++)
+                    a[q] += (((lw[e / 2] >> (16 * (e % 2))) & 0xFFFFu) != L) ? x[e] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kVnotRows; q++) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) a[q] += __shfl_xor(a[q], o);
+            if (threadIdx.x % 64 == 0) red[threadIdx.x / 64][q] = a[q];
+        }
+        __syncthreads();
+        if (threadIdx.x < kVnotRows && p0 + threadIdx.x < P)
+            vnot[p0 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                      red[2][threadIdx.x]) + red[3][threadIdx.x];
+        __syncthreads();
+    }
+}
+
 __device__ inline double pseudo_F(double sW, double sT, int64_t n, int32_t k) {
     if (k < 2 || n <= k) return NAN;
     return ((sT - sW) / (double)(k - 1)) / (sW / (double)(n - k));
@@ -202,21 +346,59 @@ size_t reduce_tmp_doubles(int64_t items, int64_t P, int32_t k) {
 
 void launch_reduce_mfma(const float *z, int64_t items, int64_t P, int32_t k, const double *w,
                         const uint8_t *bad_perm, double *tmp, double *out, hipStream_t s,
-                        const uint32_t *f16max) {
+                        const uint32_t *f16max, const Complement *cx) {
     if (P <= 0) return;
-    const int64_t total = P * k;
-    const int64_t sl = reduce_slices(items, P, k);
+    const int32_t cols = cx ? 2 * (k - 1) : k;   // z entries per grouping
+    const int64_t total = P * cols;
+    const int64_t sl = reduce_slices(items, P, cols);
     if (sl == 1) {
         hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(total, 64), 1), dim3(256), 0, s,
-                           z, items, items, P, k, tmp);
+                           z, items, items, P, cols, tmp);
     } else {
         hipLaunchKernelGGL(k_reduce_items, dim3((unsigned)ceil_div(total, 64), (unsigned)sl),
-                           dim3(256), 0, s, z, items, ceil_div(items, sl), P, k, tmp + total);
+                           dim3(256), 0, s, z, items, ceil_div(items, sl), P, cols, tmp + total);
         hipLaunchKernelGGL(k_reduce_slices, dim3(blocks_for(total, 256)), dim3(256), 0, s, tmp,
                            total, sl);
     }
-    hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
-                       bad_perm, out, f16max);
+    if (cx)
+        hipLaunchKernelGGL(k_weight_cx, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k, w,
+                           bad_perm, out, f16max, (const int32_t *)cx->L, (const double *)cx->S,
+                           (const double *)cx->vnot);
+    else
+        hipLaunchKernelGGL(k_weight_groups, dim3(blocks_for(P, 256)), dim3(256), 0, s, tmp, P, k,
+                           w, bad_perm, out, f16max);
+}
+
+int64_t complement_part_doubles(int64_t n) {
+    const int64_t panels = ceil_div(n, 128);
+    return panels * (panels + 1) * 192;
+}
+
+int64_t complement_slice_doubles(int64_t n) {
+    return 2 * kComplementSlices * ceil_div(n, 128) * 128;
+}
+
+void launch_largest_group(const uint32_t *counts, int32_t k, int32_t *L, hipStream_t s) {
+    hipLaunchKernelGGL(k_largest_group, dim3(1), dim3(64), 0, s, counts, k, L);
+}
+
+void launch_complement_sums(const Complement &cx, int64_t n, hipStream_t s) {
+    const int64_t panels = ceil_div(n, 128);
+    const int64_t n_pad = panels * 128;
+    hipLaunchKernelGGL(k_complement_slices, dim3(blocks_for(n_pad, 64), kComplementSlices),
+                       dim3(64), 0, s, (const double *)cx.rcs, n_pad, 2 * panels, cx.slices);
+    hipLaunchKernelGGL(k_complement_sums, dim3(blocks_for(n_pad, 256)), dim3(256), 0, s,
+                       (const double *)cx.slices, n_pad, cx.v, cx.r);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, (const double *)cx.r, n_pad, cx.S);
+}
+
+void launch_vnot(const Complement &cx, const uint16_t *lab, int64_t stride, int64_t n, int64_t P,
+                 hipStream_t s) {
+    if (P <= 0) return;
+    const int64_t groups = ceil_div(P, kVnotRows);
+    const unsigned g = (unsigned)(groups < 65535 ? groups : 65535);
+    hipLaunchKernelGGL(k_vnot, dim3(g), dim3(256), 0, s, lab, stride, round_up(n, 128), P,
+                       (const int32_t *)cx.L, (const double *)cx.v, cx.vnot);
 }
 
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,

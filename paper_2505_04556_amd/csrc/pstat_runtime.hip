@@ -152,7 +152,7 @@ void mfma_params(int path, int *kchunk_cols, int *ncols) {
 }
 
 void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
-               SwLayout &L) {
+               SwLayout &L, bool cx) {
     L.path = path;
     L.bad = (uint8_t *)c.take((size_t)(P > 0 ? P : 1));
     if (!is_mfma(path)) {
@@ -165,18 +165,29 @@ void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_ti
     }
     int kchunk_cols, ncols;
     mfma_params(path, &kchunk_cols, &ncols);
-    L.mp = mfma_plan(n, P, k, mfma_dtype(path), kchunk_cols, ncols, dev_info().n_cu);
+    L.mp = mfma_plan(n, P, k, mfma_dtype(path), kchunk_cols, ncols, dev_info().n_cu,
+                     cx && own_tiles);
     L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
     if (own_tiles) L.tiles = c.take(mfma_tile_bytes(n, mfma_dtype(path)));
     L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
-    L.z = (float *)c.take((size_t)L.mp.items * (P > 0 ? P : 1) * k * sizeof(float));
-    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, P, k) * sizeof(double));
+    const int32_t zc = L.mp.cx ? 2 * L.mp.kcol : k;   // z entries per grouping
+    L.z = (float *)c.take((size_t)L.mp.items * (P > 0 ? P : 1) * zc * sizeof(float));
+    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, P, zc) * sizeof(double));
+    if (L.mp.cx) {
+        L.cx.L = (int32_t *)c.take(sizeof(int32_t));
+        L.cx.rcs = (double *)c.take((size_t)complement_part_doubles(n) * sizeof(double));
+        L.cx.slices = (double *)c.take((size_t)complement_slice_doubles(n) * sizeof(double));
+        L.cx.v = (double *)c.take((size_t)L.mp.n_pad * sizeof(double));
+        L.cx.r = (double *)c.take((size_t)L.mp.n_pad * sizeof(double));
+        L.cx.S = (double *)c.take(sizeof(double));
+        L.cx.vnot = (double *)c.take((size_t)(P > 0 ? P : 1) * sizeof(double));
+    }
 }
 
-size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles) {
+size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles, bool cx) {
     Carver c{nullptr, 0, 0, true};
     SwLayout L;
-    layout_sW(c, n, P, k, path, own_tiles, L);
+    layout_sW(c, n, P, k, path, own_tiles, L, cx);
     return c.used + 256;
 }
 
@@ -212,18 +223,27 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
         launch_stage_labels_pm(g, n, P, L.mp.n_pad, L.mp.P_pad, limit, L.lab, L.bad, err_flag, s);
         if ((rc = check_launch("label staging"))) return rc;
     }
+    if (L.mp.cx && tiles) return fail(PSTAT_EINVAL, "complement form needs the pre-pass");
     if (!tiles) {
-        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT, samples);
+        launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT, samples,
+                            L.mp.cx ? L.cx.rcs : nullptr);
         if ((rc = check_launch("mfma prepass"))) return rc;
         tiles = L.tiles;
     }
+    if (L.mp.cx) {
+        // *L.cx.L (the largest group) was set by the caller
+        launch_complement_sums(L.cx, n, s);
+        launch_vnot(L.cx, L.lab, L.mp.n_pad, n, P, s);
+        if ((rc = check_launch("complement sums"))) return rc;
+    }
     KernelTimer timer(s, timed);
-    if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s))
+    if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s, L.mp.cx ? L.cx.L : nullptr))
         return fail(PSTAT_EINVAL, "no MFMA kernel for %d columns", L.mp.ncols);
     timer.stop(s);
     if ((rc = check_launch("mfma s_W"))) return rc;
     launch_reduce_mfma(L.z, L.mp.items, P, k, w, L.bad, L.tmp, out, s,
-                       L.mp.dtype == 1 ? f16_max_cell(tiles, n) : nullptr);
+                       L.mp.dtype == 1 ? f16_max_cell(tiles, n) : nullptr,
+                       L.mp.cx ? &L.cx : nullptr);
     return check_launch("mfma reduce");
 }
 
@@ -579,7 +599,7 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
     const size_t head = (size_t)round_up((int64_t)dry.used, 256) + 256;
     // s_W workspace, then the FP64 recheck's partials (the recheck may read
     // the staged labels, so the two must not overlap)
-    const size_t swb = sW_bytes(n, R, k, path, true);
+    const size_t swb = sW_bytes(n, R, k, path, true, true);
     const size_t fpb = few_partial_bytes(n, R);
     char *ws;
     if ((rc = acquire_workspace(head + swb + fpb, &ws))) return rc;
@@ -590,7 +610,7 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
 
     Carver c{ws + head, swb, 0, false};
     SwLayout L;
-    layout_sW(c, n, R, k, path, true, L);
+    layout_sW(c, n, R, k, path, true, L, true);
     // MFMA forms: the shuffle writes the permutations straight into the
     // staged u16 layout (row 0 the observed grouping, rows past R padding)
     bool staged = false;
@@ -610,6 +630,9 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         }
     }
     if (!staged && (rc = prepare_test(h, n, grouping, k, n_perms, seed, max_label))) return rc;
+    // Complement form: every row is a permutation of the observed grouping,
+    // so all share its group sizes; the largest group gets no columns.
+    if (is_mfma(path) && L.mp.cx) launch_largest_group(h.counts, k, L.cx.L, s);
     // The MFMA forms' pre-pass also leaves s_T and the FP64 s_W of the
     // observed grouping and the first permutations (the recheck's samples).
     const bool mf = is_mfma(path);

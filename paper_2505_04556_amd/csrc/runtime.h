@@ -93,15 +93,18 @@ struct SwLayout {
     double *partial = nullptr;   // plain: [chunks][P_pad]
     void *tiles = nullptr;       // MFMA: pre-squared tiles (unless registered)
     int32_t *tab = nullptr;      // MFMA: work-item table
-    float *z = nullptr;          // MFMA: [items][P][k]
-    double *tmp = nullptr;       // MFMA: [P][k]
+    float *z = nullptr;          // MFMA: [items][P][k] (complement: [items][P][k-1][2])
+    double *tmp = nullptr;       // MFMA: [P][k] (complement: [P][k-1][2])
+    Complement cx{};             // MFMA complement form (mp.cx)
     PlainPlan pp{};
     MfmaPlan mp{};
 };
 
+// cx: the MFMA forms may use the complement form (every grouping must have
+// the group sizes of the first; the pre-pass must run, not registered tiles).
 void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_tiles,
-               SwLayout &L);
-size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles);
+               SwLayout &L, bool cx = false);
+size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles, bool cx = false);
 
 // Event pair around the main kernel when this thread is profiling.
 struct KernelTimer {

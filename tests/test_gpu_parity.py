@@ -416,6 +416,61 @@ def test_permanova_label_widths(ps, path, n, k, P):
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
 
 
+# Whole test on the MFMA forms: the largest group gets no columns; its block
+# is the matrix total minus the other groups' rows.  Largest group first, in
+# the middle, last and tied; k from 2 to 16 (one or two columns per
+# permutation take 256-column work-groups; the three-part split with k = 2
+# keeps all columns).  The fast values (rows past the 16 FP64 samples) meet
+# the form's tolerance and agree with the same rows through pstat_sW, which
+# always uses every column.
+MFMA_PATHS = ["mfma_split_bf16", "mfma_split3_bf16", "mfma_f16", "mfma_bf16"]
+
+
+@pytest.mark.parametrize("path", MFMA_PATHS)
+@pytest.mark.parametrize("sizes", [[400, 100], [100, 400], [60, 300, 120], [120, 120, 60],
+                                   [50, 70, 300, 90, 40], [30] * 16])
+def test_permanova_complement_form(ps, path, sizes):
+    import torch
+    n, k, P = sum(sizes), len(sizes), 200
+    D = synth.uniform_matrix(n, 900 + n)
+    base = synth.base_labels(sizes)
+    seed = 31 + k
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+    rows = np.vstack([base, oracle.permute(base, P, seed)])
+    full = ps.pstat_sW_k(Dd, to_dev(rows)[0], k, to_dev(synth.inv_group_sizes(sizes))[0])
+    ps.pstat_set_path("auto")
+    sw, full, res = sw.cpu().numpy(), full.cpu().numpy(), res.cpu().numpy()
+    assert max_rel(sw[1:], ref["sW_perm"]) <= TOL[path]
+    assert max_rel(sw[16:], full[16:]) <= 2 * TOL[path]
+    assert res[1] == ref["p"], (res[1], ref["p"], rechecked)
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+
+
+# Dyadic inputs and power-of-two group sizes keep every sum exact, the
+# complement's subtraction included: the whole test's s_W equal the oracle's
+# bit for bit on every MFMA form.
+@pytest.mark.parametrize("path", MFMA_PATHS)
+def test_permanova_complement_dyadic_bit_exact(ps, path):
+    import torch
+    sizes = [16, 64, 32, 16]
+    n, k, P, seed = sum(sizes), len(sizes), 90, 8
+    D = synth.dyadic_matrix(n, 5)
+    base = synth.base_labels(sizes)
+    rows = np.vstack([base, oracle.permute(base, P, seed)])
+    ref = oracle.sW(D, rows, synth.inv_group_sizes(sizes))
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    sw = sw.cpu().numpy()
+    assert np.array_equal(sw, ref), f"max rel err {max_rel(sw, ref):.3e}"
+
+
 # The observed grouping and the first 15 permutations are recomputed in FP64
 # (inside the pre-pass on the MFMA forms, by the recheck kernel on the plain
 # ones) and written back into sW_all: those entries match the oracle to FP64
