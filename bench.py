@@ -371,7 +371,10 @@ def main() -> int:
     R = P + 1
     if best.startswith("mfma"):
         s = 3 if "split3" in best else 2 if "split" in best else 1
-        work = 2.0 * k * s * pairs * R
+        # the whole test's MFMA kernel has k - 1 one-hot columns per grouping
+        # from three groups on (the largest group comes from the complement)
+        kc = k - 1 if k >= 3 else k
+        work = 2.0 * kc * s * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12
         traffic = None
         if best == "mfma_split_bf16" and args.config == 1:
@@ -382,7 +385,7 @@ def main() -> int:
                     traffic_unit="HBM bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, "
                                  "calibrated on a 1 GiB copy)",
                     kernel=f"k_mfma<{s}> ({best})", kernel_ms=round(kern_ms, 4),
-                    work_per_launch=f"{2 * k * s} flop x {pairs} pairs x {R} groupings")
+                    work_per_launch=f"{2 * kc * s} flop x {pairs} pairs x {R} groupings")
     else:
         work = PLAIN_OPS_PER_PAIRPERM * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12

@@ -74,8 +74,10 @@ struct JobDesc {              // one staged problem, device-resident
     const void *tiles;        // pre-squared tiles
     const uint16_t *lab_pm;   // u16 [P_pad_m][n_pad_m], permutation-major
     const int32_t *tab;       // work-item table
-    float *z;                 // [items][R][k]
+    float *z;                 // [items][R][k], complement form [items][R][k-1][2]
     int64_t comp_units, kb_total, n_pad_m, R;
+    int32_t cx;               // complement form (group *Lp has no columns)
+    const int32_t *Lp;
 };
 struct UnitDesc {             // one work-group's share of one job: plain
     int32_t job, chunk, pgroup;   // (tile chunk, permutation group); MFMA

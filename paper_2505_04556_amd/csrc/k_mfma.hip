@@ -419,14 +419,14 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 // even number of K blocks), so every access names its buffer statically and
 // the compiler can see that reads of one buffer do not depend on the copy into
 // the other.
-// CX: complement form -- kcol = k - 1 columns per grouping, for the groups
-// other than L; the epilogue writes two sums per column (rows of the
-// column's group, rows not in L).  Otherwise kcol = k.
-template <int DT, int NF, int LQ, bool CX>
+// cx: complement form -- kcol = k - 1 columns per grouping, for the groups
+// other than Lg; the epilogue writes two sums per column (rows of the
+// column's group, rows not in Lg).  Otherwise kcol = k.
+template <int DT, int NF, int LQ>
 __device__ __attribute__((always_inline)) inline void mfma_unit(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t item, int64_t nb, const uint16_t *__restrict__ lab,
-    int64_t n_pad, int32_t kcol, int32_t Lg, int64_t P, float *__restrict__ z) {
+    int64_t n_pad, bool cx, int32_t kcol, int32_t Lg, int64_t P, float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
     constexpr int NC = DT == 3 ? 3 : DT == 2 ? 2 : 1;   // A components (hi, [mid,] lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
@@ -458,7 +458,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
         const int64_t c = nb * COLS + wave * (NF * 32) + nf * 32 + col;
         const int64_t p = c / kcol;
         uint32_t g = (uint32_t)(c - p * kcol);
-        if (CX && g >= (uint32_t)Lg) g++;   // the column's group skips L
+        if (cx && g >= (uint32_t)Lg) g++;   // the column's group skips Lg
         gg[nf] = g | (g << 16);
         // K step s of a block uses rows 8s + 32*half + 0..7: chunk s + 4*half
         lslot[nf] = (int)(p - p_lo) * kLStride + 4 * half;
@@ -626,13 +626,13 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                 for (int b = 0; b < 4; b++) {
                     const float y = acc[rb][nf][4 * a + b];
                     zs += (lab4[b] == g) ? y : 0.0f;
-                    if (CX) zn += (lab4[b] != (uint32_t)Lg) ? y : 0.0f;
+                    zn += (lab4[b] != (uint32_t)Lg) ? y : 0.0f;
                 }
             }
         }
         zs += __shfl_xor(zs, 32);
         const int64_t p = p_lo + slot0 / kLStride;
-        if (CX) {
+        if (cx) {
             zn += __shfl_xor(zn, 32);
             const uint32_t gc = g - (g > (uint32_t)Lg ? 1u : 0u);   // column within p
             if (half == 0 && p < P)
@@ -644,19 +644,19 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     }
 }
 
-template <int DT, int NF, int LQ, bool CX>
+template <int DT, int NF, int LQ>
 __global__ __launch_bounds__(256) void k_mfma(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
-    const uint16_t *__restrict__ lab, int64_t n_pad, int32_t kcol, const int32_t *__restrict__ Lp,
-    int64_t P, float *__restrict__ z) {
+    const uint16_t *__restrict__ lab, int64_t n_pad, int cx, int32_t kcol,
+    const int32_t *__restrict__ Lp, int64_t P, float *__restrict__ z) {
     const int64_t gpad = gridDim.x;
     const int64_t bid = blockIdx.x;
     const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
     if (logical >= grid_real) return;
-    const int32_t Lg = CX ? *Lp : 0;
-    mfma_unit<DT, NF, LQ, CX>(tiles, comp_units, kb_total, tab, logical / nblocks,
-                              logical % nblocks, lab, n_pad, kcol, Lg, P, z);
+    const int32_t Lg = cx ? *Lp : 0;
+    mfma_unit<DT, NF, LQ>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
+                          lab, n_pad, cx != 0, kcol, Lg, P, z);
 }
 
 // Label-copy rounds for the permutations that COLS columns of k groups can
@@ -687,8 +687,10 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
     if (logical >= *count) return;
     const UnitDesc u = units[logical];
     const JobDesc &j = jobs[u.job];
-    mfma_unit<2, 4, 10, false>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
-                               u.pgroup, j.lab_pm, j.n_pad_m, j.k, 0, j.R, j.z);
+    const bool cx = j.cx != 0;
+    mfma_unit<2, 4, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
+                        u.pgroup, j.lab_pm, j.n_pad_m, cx, cx ? j.k - 1 : j.k, cx ? *j.Lp : 0, j.R,
+                        j.z);
 }
 
 } // namespace
@@ -731,7 +733,10 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
         const int lq = lq_bin(cols, kc);
         return lq > 0 && mfma_lds_fits(dtype, cols / 128, lq);
     };
-    pl.cx = cx && k >= 2 && (fits(pl.ncols, k - 1) || fits(256, k - 1));
+    // (Two groups would leave one column per permutation, which needs
+    // 256-column work-groups; the serving kernel has 512 only, and the whole
+    // test and serving must agree bit for bit, so k = 2 keeps both columns.)
+    pl.cx = cx && k >= 3 && (fits(pl.ncols, k - 1) || fits(256, k - 1));
     pl.kcol = pl.cx ? k - 1 : k;
     if (!fits(pl.ncols, pl.kcol)) pl.ncols = 256;
     pl.N = (int64_t)pl.kcol * P;
@@ -792,14 +797,9 @@ template <int DT, int NF, int LQ>
 void launch_mfma_t(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
                    int64_t grid_real, int64_t gpad, const uint16_t *lab, const int32_t *Lp,
                    int64_t P, float *z, hipStream_t s) {
-    if (pl.cx)
-        hipLaunchKernelGGL((k_mfma<DT, NF, LQ, true>), dim3((unsigned)gpad), dim3(256), 0, s, t,
-                           comp_units, pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad,
-                           pl.kcol, Lp, P, z);
-    else
-        hipLaunchKernelGGL((k_mfma<DT, NF, LQ, false>), dim3((unsigned)gpad), dim3(256), 0, s, t,
-                           comp_units, pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad,
-                           pl.kcol, Lp, P, z);
+    hipLaunchKernelGGL((k_mfma<DT, NF, LQ>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
+                       pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad, pl.cx ? 1 : 0,
+                       pl.kcol, Lp, P, z);
 }
 
 template <int DT, int NF>

@@ -27,6 +27,7 @@ struct Job {
     double *partial = nullptr;
     float *z = nullptr;
     double *tmp = nullptr;
+    Complement cx{};               // MFMA complement form (mp.cx)
     uint8_t *bad = nullptr;
     int64_t units = 0;
     int64_t split = 1;             // units are (a, b) with b in [0, split)
@@ -72,6 +73,7 @@ struct JobLayout {
     int32_t *tab = nullptr;
     float *z = nullptr;
     double *tmp = nullptr;
+    Complement cx{};
 };
 
 void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, int kind, JobLayout &L) {
@@ -84,12 +86,24 @@ void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, int kind, JobL
         L.partial = (double *)c.take((size_t)L.pl.chunks * L.pl.P_pad * sizeof(double));
         return;
     }
-    L.mp = mfma_plan(n, R, k, 2, 0, 512, dev_info().n_cu);
+    // the same plan as the whole-test entry point's (complement form from
+    // three groups on), so a job's results equal that call's bit for bit
+    L.mp = mfma_plan(n, R, k, 2, 0, 512, dev_info().n_cu, true);
     L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
     L.tiles = c.take(mfma_tile_bytes(n, 2));
     L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
-    L.z = (float *)c.take((size_t)L.mp.items * R * k * sizeof(float));
-    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, R, k) * sizeof(double));
+    const int32_t zc = L.mp.cx ? 2 * L.mp.kcol : k;   // z entries per grouping
+    L.z = (float *)c.take((size_t)L.mp.items * R * zc * sizeof(float));
+    L.tmp = (double *)c.take(reduce_tmp_doubles(L.mp.items, R, zc) * sizeof(double));
+    if (L.mp.cx) {
+        L.cx.L = (int32_t *)c.take(sizeof(int32_t));
+        L.cx.rcs = (double *)c.take((size_t)complement_part_doubles(n) * sizeof(double));
+        L.cx.slices = (double *)c.take((size_t)complement_slice_doubles(n) * sizeof(double));
+        L.cx.v = (double *)c.take((size_t)L.mp.n_pad * sizeof(double));
+        L.cx.r = (double *)c.take((size_t)L.mp.n_pad * sizeof(double));
+        L.cx.S = (double *)c.take(sizeof(double));
+        L.cx.vnot = (double *)c.take((size_t)R * sizeof(double));
+    }
 }
 
 int job_kind(int path, int64_t n, int32_t k) {
@@ -263,7 +277,13 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
         prc.k = n_groups;
         prc.part = L.head.rcp;
         prc.out = L.head.vals;
-        launch_mfma_prepass(mat, n, 2, L.tiles, s, L.head.sTp, L.head.sT, &prc);
+        if (L.mp.cx) launch_largest_group(L.head.counts, n_groups, L.cx.L, s);
+        launch_mfma_prepass(mat, n, 2, L.tiles, s, L.head.sTp, L.head.sT, &prc,
+                            L.mp.cx ? L.cx.rcs : nullptr);
+        if (L.mp.cx) {
+            launch_complement_sums(L.cx, n, s);
+            launch_vnot(L.cx, L.lab, L.mp.n_pad, n, R, s);
+        }
         launch_item_table(L.mp, L.tab, s);
         d.tiles = L.tiles;
         d.lab_pm = L.lab;
@@ -272,6 +292,8 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
         d.comp_units = L.mp.panels * (L.mp.panels + 1);
         d.kb_total = L.mp.kb_total;
         d.n_pad_m = L.mp.n_pad;
+        d.cx = L.mp.cx ? 1 : 0;
+        d.Lp = L.cx.L;
     }
     if ((rc = check_launch("job staging"))) return rc;
     HIP_TRY(hipMemcpyAsync(sv->jobs_dev + slot, &d, sizeof(JobDesc), hipMemcpyHostToDevice, s));
@@ -290,6 +312,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     J.partial = L.partial;
     J.z = L.z;
     J.tmp = L.tmp;
+    J.cx = L.cx;
     J.bad = L.bad;
     if (kind == 0) {
         J.units = L.pl.chunks * L.pl.pgroups;
@@ -382,7 +405,8 @@ int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all
     if (J.kind == 0)
         launch_reduce_plain(J.partial, J.pl.chunks, J.pl.P_pad, R, J.bad, J.head.sw, s);
     else
-        launch_reduce_mfma(J.z, J.mp.items, R, J.k, J.head.w, J.bad, J.tmp, J.head.sw, s);
+        launch_reduce_mfma(J.z, J.mp.items, R, J.k, J.head.w, J.bad, J.tmp, J.head.sw, s, nullptr,
+                           J.mp.cx ? &J.cx : nullptr);
     if ((rc = check_launch("job reduce"))) return rc;
     const size_t region = few_partial_bytes(J.n, R);
     char *ws;
