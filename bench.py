@@ -372,8 +372,8 @@ def main() -> int:
     if best.startswith("mfma"):
         s = 3 if "split3" in best else 2 if "split" in best else 1
         # the whole test's MFMA kernel has k - 1 one-hot columns per grouping
-        # from three groups on (the largest group comes from the complement)
-        kc = k - 1 if k >= 3 else k
+        # (the largest group comes from the complement)
+        kc = k - 1
         work = 2.0 * kc * s * pairs * R
         achieved = work / (kern_ms / 1e3) / 1e12
         traffic = None

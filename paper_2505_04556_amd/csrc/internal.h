@@ -69,7 +69,7 @@ struct JobDesc {              // one staged problem, device-resident
     const double *w;
     double *partial;          // [chunks][P_pad]
     int64_t n, nt, n_tiles, tiles_per_chunk, P_pad;
-    int32_t k, kind;          // kind: 0 plain FP32, 1 MFMA split BF16
+    int32_t k, kind;          // kind: 0 plain FP32, 1 / 2 MFMA split BF16 (512 / 256 columns)
     // MFMA form (split BF16, 512 columns per work-group)
     const void *tiles;        // pre-squared tiles
     const uint16_t *lab_pm;   // u16 [P_pad_m][n_pad_m], permutation-major
@@ -97,8 +97,9 @@ void launch_reduce_partials(const double *partial, int64_t runs, int64_t stride,
                             double *out, hipStream_t s);
 void launch_plain_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                            int64_t max_units, hipStream_t s);
+// ncols: the column count (512 or 256) every job of the unit list was planned with
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
-                          int64_t max_units, hipStream_t s);
+                          int64_t max_units, hipStream_t s, int ncols = 512);
 // partial[chunk][P_pad] FP64 from u16 [n_pad][P_pad] labels.  Perm lane q of
 // the label table is permutation q.  f64 selects the FP64 instantiation.
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,

@@ -677,7 +677,10 @@ int lq_bin(int cols, int32_t k) {
 }
 
 // Work-list form (serving): block b runs unit units[b] = (job, item, column
-// block) of a split-BF16 job in the job table (labels staged for any k >= 2).
+// block) of a split-BF16 job in the job table; NF = 4 for the jobs planned
+// with 512 columns per work-group, 2 for those with 256 (labels staged for
+// any number of columns per grouping those plans allow).
+template <int NF>
 __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict__ jobs,
                                                       const UnitDesc *__restrict__ units,
                                                       const int32_t *__restrict__ count) {
@@ -688,9 +691,9 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
     const UnitDesc u = units[logical];
     const JobDesc &j = jobs[u.job];
     const bool cx = j.cx != 0;
-    mfma_unit<2, 4, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
-                        u.pgroup, j.lab_pm, j.n_pad_m, cx, cx ? j.k - 1 : j.k, cx ? *j.Lp : 0, j.R,
-                        j.z);
+    mfma_unit<2, NF, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
+                         u.pgroup, j.lab_pm, j.n_pad_m, cx, cx ? j.k - 1 : j.k, cx ? *j.Lp : 0,
+                         j.R, j.z);
 }
 
 } // namespace
@@ -733,10 +736,7 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
         const int lq = lq_bin(cols, kc);
         return lq > 0 && mfma_lds_fits(dtype, cols / 128, lq);
     };
-    // (Two groups would leave one column per permutation, which needs
-    // 256-column work-groups; the serving kernel has 512 only, and the whole
-    // test and serving must agree bit for bit, so k = 2 keeps both columns.)
-    pl.cx = cx && k >= 3 && (fits(pl.ncols, k - 1) || fits(256, k - 1));
+    pl.cx = cx && k >= 2 && (fits(pl.ncols, k - 1) || fits(256, k - 1));
     pl.kcol = pl.cx ? k - 1 : k;
     if (!fits(pl.ncols, pl.kcol)) pl.ncols = 256;
     pl.N = (int64_t)pl.kcol * P;
@@ -848,9 +848,14 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
 }
 
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
-                          int64_t max_units, hipStream_t s) {
+                          int64_t max_units, hipStream_t s, int ncols) {
     const int64_t gpad = round_up(max_units > 0 ? max_units : 1, 8);
-    hipLaunchKernelGGL(k_mfma_worklist, dim3((unsigned)gpad), dim3(256), 0, s, jobs, units, count);
+    if (ncols == 256)
+        hipLaunchKernelGGL(k_mfma_worklist<2>, dim3((unsigned)gpad), dim3(256), 0, s, jobs, units,
+                           count);
+    else
+        hipLaunchKernelGGL(k_mfma_worklist<4>, dim3((unsigned)gpad), dim3(256), 0, s, jobs, units,
+                           count);
 }
 
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s) {

@@ -14,9 +14,12 @@ namespace pstat {
 namespace rt {
 namespace {
 
+constexpr int kKinds = 3;
+
 struct Job {
     bool live = false;
-    int kind = 0;                  // 0 plain FP32, 1 MFMA split BF16
+    int kind = 0;                  // 0 plain FP32, 1 MFMA split BF16 (512-column
+                                   // work-groups), 2 the same with 256 columns
     const float *mat = nullptr;
     int64_t n = 0, n_perms = 0;
     int32_t k = 0;
@@ -38,10 +41,11 @@ struct Server {
     int64_t max_jobs = 0, max_units = 0;
     JobDesc *jobs_dev = nullptr;
     JobDesc *jobs_host = nullptr;           // pinned, one entry per slot
-    // per alternating slot b: unit lists of the plain [0] and MFMA [1] kinds
-    UnitDesc *units_dev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // per alternating slot b: unit lists of the plain [0] and the two MFMA
+    // [1], [2] kinds
+    UnitDesc *units_dev[2][kKinds] = {};
     int32_t *count_dev[2] = {nullptr, nullptr};    // [kind] counts of slot b
-    UnitDesc *units_host[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // pinned
+    UnitDesc *units_host[2][kKinds] = {};          // pinned
     int32_t *count_host[2] = {nullptr, nullptr};   // pinned
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -86,8 +90,9 @@ void layout_job(Carver &c, int64_t n, int64_t n_perms, int32_t k, int kind, JobL
         L.partial = (double *)c.take((size_t)L.pl.chunks * L.pl.P_pad * sizeof(double));
         return;
     }
-    // the same plan as the whole-test entry point's (complement form from
-    // three groups on), so a job's results equal that call's bit for bit
+    // the same plan as the whole-test entry point's (complement form; 256
+    // columns per work-group with two groups), so a job's results equal that
+    // call's bit for bit
     L.mp = mfma_plan(n, R, k, 2, 0, 512, dev_info().n_cu, true);
     L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
     L.tiles = c.take(mfma_tile_bytes(n, 2));
@@ -118,7 +123,7 @@ void destroy_server(Server *sv) {
         if (sv->exec[b]) (void)hipGraphExecDestroy(sv->exec[b]);
         if (sv->graph[b]) (void)hipGraphDestroy(sv->graph[b]);
         if (sv->done[b]) (void)hipEventDestroy(sv->done[b]);
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < kKinds; t++) {
             if (sv->units_dev[b][t]) (void)hipFree(sv->units_dev[b][t]);
             if (sv->units_host[b][t]) (void)hipHostFree(sv->units_host[b][t]);
         }
@@ -162,7 +167,7 @@ int pstat_serve_create(int64_t max_jobs, int64_t max_units, int64_t *server) {
         return bail(e, "hipHostMalloc(job table)");
     memset(sv->jobs_host, 0, sizeof(JobDesc) * max_jobs);
     for (int b = 0; b < 2; b++) {
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < kKinds; t++) {
             if ((e = hipMalloc((void **)&sv->units_dev[b][t], sizeof(UnitDesc) * max_units)) !=
                 hipSuccess)
                 return bail(e, "hipMalloc(units)");
@@ -175,8 +180,7 @@ int pstat_serve_create(int64_t max_jobs, int64_t max_units, int64_t *server) {
             return bail(e, "hipMalloc(count)");
         if ((e = hipHostMalloc((void **)&sv->count_host[b], 64, hipHostMallocDefault)) != hipSuccess)
             return bail(e, "hipHostMalloc(count)");
-        sv->count_host[b][0] = 0;
-        sv->count_host[b][1] = 0;
+        for (int t = 0; t < kKinds; t++) sv->count_host[b][t] = 0;
         if ((e = hipEventCreateWithFlags(&sv->done[b], hipEventDisableTiming)) != hipSuccess)
             return bail(e, "hipEventCreate");
     }
@@ -227,7 +231,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     if ((rc = check_dev_ptr(mat, "mat")) || (rc = check_dev_ptr(grouping, "grouping")) ||
         (rc = check_dev_ptr(scratch, "scratch")))
         return rc;
-    const int kind = job_kind(path, n, n_groups);
+    int kind = job_kind(path, n, n_groups);
     if (kind < 0) return fail(PSTAT_EINVAL, "serving jobs run the plain FP32 or split-BF16 MFMA form");
     const size_t need = pstat_job_bytes(n, n_perms, n_groups, path);
     if (scratch_bytes < need)
@@ -243,6 +247,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     Carver c{(char *)scratch, scratch_bytes, 0, false};
     JobLayout L;
     layout_job(c, n, n_perms, n_groups, kind, L);
+    if (kind == 1 && L.mp.ncols == 256) kind = 2;   // one column per permutation: k = 2
     const int64_t R = n_perms + 1;
     if ((rc = prepare_test(L.head, n, grouping, n_groups, n_perms, seed, max_label))) return rc;
     hipStream_t s = tls.stream;
@@ -343,7 +348,7 @@ int pstat_serve_round(int64_t server, const int64_t *units, int64_t count) {
     // Host pairs (job, unit) -> (job, a, b) in the list of the job's kind:
     // plain (tile chunk, permutation group), MFMA (work item, column block);
     // a job's units are numbered a-major so neighbouring units share data.
-    int32_t cnt[2] = {0, 0};
+    int32_t cnt[kKinds] = {0, 0, 0};
     for (int64_t i = 0; i < count; i++) {
         const int64_t j = units[2 * i], u = units[2 * i + 1];
         if (j < 0 || j >= sv->max_jobs || !sv->jobs[j].live)
@@ -355,26 +360,27 @@ int pstat_serve_round(int64_t server, const int64_t *units, int64_t count) {
         sv->units_host[b][J.kind][cnt[J.kind]++] =
             UnitDesc{(int32_t)j, (int32_t)(u / J.split), (int32_t)(u % J.split)};
     }
-    sv->count_host[b][0] = cnt[0];
-    sv->count_host[b][1] = cnt[1];
+    for (int t = 0; t < kKinds; t++) sv->count_host[b][t] = cnt[t];
     if (!sv->exec[b]) {
         hipStream_t s = tls.stream;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-        hipError_t e[6];
-        e[0] = hipMemcpyAsync(sv->units_dev[b][0], sv->units_host[b][0],
-                              sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
-        e[1] = hipMemcpyAsync(sv->units_dev[b][1], sv->units_host[b][1],
-                              sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
-        e[2] = hipMemcpyAsync(sv->count_dev[b], sv->count_host[b], 2 * sizeof(int32_t),
+        hipError_t e[8];
+        for (int t = 0; t < kKinds; t++)
+            e[t] = hipMemcpyAsync(sv->units_dev[b][t], sv->units_host[b][t],
+                                  sizeof(UnitDesc) * sv->max_units, hipMemcpyHostToDevice, s);
+        e[3] = hipMemcpyAsync(sv->count_dev[b], sv->count_host[b], kKinds * sizeof(int32_t),
                               hipMemcpyHostToDevice, s);
         launch_plain_worklist(sv->jobs_dev, sv->units_dev[b][0], sv->count_dev[b], sv->max_units, s);
-        e[3] = hipGetLastError();
-        launch_mfma_worklist(sv->jobs_dev, sv->units_dev[b][1], sv->count_dev[b] + 1,
-                             sv->max_units, s);
         e[4] = hipGetLastError();
+        launch_mfma_worklist(sv->jobs_dev, sv->units_dev[b][1], sv->count_dev[b] + 1,
+                             sv->max_units, s, 512);
+        e[5] = hipGetLastError();
+        launch_mfma_worklist(sv->jobs_dev, sv->units_dev[b][2], sv->count_dev[b] + 2,
+                             sv->max_units, s, 256);
+        e[6] = hipGetLastError();
         hipGraph_t g = nullptr;
-        e[5] = hipStreamEndCapture(s, &g);
-        for (int q = 0; q < 6; q++)
+        e[7] = hipStreamEndCapture(s, &g);
+        for (int q = 0; q < 8; q++)
             if (e[q] != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
                 return hip_fail(e[q], "capturing the serving round");

@@ -155,7 +155,9 @@ class GpuExecutor(Executor):
                 block = torch.empty(int(reserve_bytes), dtype=torch.uint8, device=self.device)
                 del block
         rng = np.random.default_rng(0)
-        for k in (3, 40):     # split BF16 (k <= 16) and plain under "auto"
+        # split BF16 with 512- and 256-column work-groups (k = 3, 2; k <= 16)
+        # and plain (k = 40) under "auto"
+        for k in (3, 2, 40):
             n = 640
             g = np.concatenate([np.arange(k), rng.integers(0, k, size=n - k)]).astype(np.int32)
 
