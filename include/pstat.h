@@ -76,6 +76,19 @@ int pstat_init(int device);
 /* Stream (a hipStream_t, NULL = null stream) for this thread's later calls. */
 int pstat_set_stream(void *hip_stream);
 
+/* ---- matrix layouts --------------------------------------------------------
+ * Every call reads D only above the diagonal (section 2, Algorithm 1), so it
+ * can be given either as the full row-major n x n square or as that strict
+ * upper triangle alone, packed row after row: row i holds d_i,i+1 .. d_i,n-1
+ * and starts at float i (2n - i - 1) / 2, n (n - 1) / 2 floats in all (half
+ * the memory, which is what lets larger n fit on one device).  The layout
+ * applies to the `mat` of this thread's later calls (pstat_sW, pstat_sW_k,
+ * pstat_sT, pstat_permanova, pstat_matrix_register, pstat_job_create);
+ * results are bit-identical in both.  PSTAT_EINVAL for an unknown layout. */
+#define PSTAT_LAYOUT_SQUARE 0
+#define PSTAT_LAYOUT_UPPER_PACKED 1
+int pstat_set_matrix_layout(int layout);
+
 /* Form used by pstat_sW / pstat_sW_k / pstat_permanova on this thread.
  * PSTAT_PATH_AUTO (default) = the tuned choice for the problem shape.  The
  * MFMA forms need at least two groups: with a single group the plain FP32

@@ -12,6 +12,7 @@ torch supplies device memory and the current stream only.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -28,6 +29,9 @@ PSTAT_ENOMEM = -4
 PSTAT_EHIP = -5
 PSTAT_EPTR = -6
 PSTAT_ESTATE = -7
+
+PSTAT_LAYOUT_SQUARE = 0
+PSTAT_LAYOUT_UPPER_PACKED = 1
 
 PSTAT_PATH_AUTO = -1
 PSTAT_PATH_PLAIN_F32 = 0
@@ -71,6 +75,7 @@ _SIGS = {
     "pstat_last_error": ([], ctypes.c_char_p),
     "pstat_init": ([_int], _int),
     "pstat_set_stream": ([_P], _int),
+    "pstat_set_matrix_layout": ([_int], _int),
     "pstat_set_path": ([_int], _int),
     "pstat_set_tuning": ([_int, _int, _int], _int),
     "pstat_set_workspace": ([_P, _size], _int),
@@ -132,6 +137,29 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> int:
     return t.data_ptr()
 
 
+def packed_n(length: int) -> int:
+    """n of a strict upper triangle packed into `length` = n (n - 1) / 2 floats."""
+    n = (1 + math.isqrt(1 + 8 * int(length))) // 2
+    if n < 2 or n * (n - 1) // 2 != length:
+        raise PstatError(PSTAT_EINVAL, f"{length} is not n (n - 1) / 2 for any n >= 2")
+    return n
+
+
+def _mat(mat: torch.Tensor) -> tuple[int, int]:
+    """Pointer and n of a matrix argument, setting this thread's layout: an
+    n x n tensor is the square layout, a 1-D tensor of n (n - 1) / 2 floats
+    the packed strict upper triangle."""
+    ptr = _dev(mat, torch.float32, "mat")
+    if mat.dim() == 2 and mat.shape[0] == mat.shape[1]:
+        layout, n = PSTAT_LAYOUT_SQUARE, mat.shape[0]
+    elif mat.dim() == 1:
+        layout, n = PSTAT_LAYOUT_UPPER_PACKED, packed_n(mat.numel())
+    else:
+        raise PstatError(PSTAT_EINVAL, f"mat must be n x n or packed 1-D, got {tuple(mat.shape)}")
+    _check(_lib.pstat_set_matrix_layout(layout))
+    return ptr, n
+
+
 def pstat_version() -> int:
     return int(_lib.pstat_version())
 
@@ -177,12 +205,12 @@ def pstat_workspace_bytes(n: int, n_perms: int, n_groups: int, path=PSTAT_PATH_A
 def pstat_sW(mat: torch.Tensor, groupings: torch.Tensor, inv_group_sizes: torch.Tensor,
              out: torch.Tensor | None = None) -> torch.Tensor:
     """s_W of every grouping row (validates labels; synchronises once)."""
-    n = mat.shape[0]
     P = groupings.shape[0] if groupings.dim() == 2 else 1
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
-    _check(_lib.pstat_sW(_dev(mat, torch.float32, "mat"), n,
+    mp, n = _mat(mat)
+    _check(_lib.pstat_sW(mp, n,
                          _dev(groupings, torch.int32, "groupings"), P,
                          _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
                          _dev(out, torch.float64, "out")))
@@ -191,12 +219,12 @@ def pstat_sW(mat: torch.Tensor, groupings: torch.Tensor, inv_group_sizes: torch.
 
 def pstat_sW_k(mat, groupings, n_groups: int, inv_group_sizes, out=None) -> torch.Tensor:
     """s_W with the number of groups given; asynchronous."""
-    n = mat.shape[0]
     P = groupings.shape[0] if groupings.dim() == 2 else 1
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
-    _check(_lib.pstat_sW_k(_dev(mat, torch.float32, "mat"), n,
+    mp, n = _mat(mat)
+    _check(_lib.pstat_sW_k(mp, n,
                            _dev(groupings, torch.int32, "groupings"), P, int(n_groups),
                            _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
                            _dev(out, torch.float64, "out")))
@@ -212,7 +240,8 @@ def pstat_sT(mat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
-    _check(_lib.pstat_sT(_dev(mat, torch.float32, "mat"), mat.shape[0],
+    mp, n = _mat(mat)
+    _check(_lib.pstat_sT(mp, n,
                          _dev(out, torch.float64, "s_T")))
     return out
 
@@ -269,7 +298,8 @@ def pstat_permanova(mat: torch.Tensor, grouping: torch.Tensor, n_groups: int, n_
     _ready(mat.device)
     rechecked = _i64(0)
     sw_ptr = _dev(sW_all, torch.float64, "sW_all") if sW_all is not None else None
-    _check(_lib.pstat_permanova(_dev(mat, torch.float32, "mat"), mat.shape[0],
+    mp, n = _mat(mat)
+    _check(_lib.pstat_permanova(mp, n,
                                 _dev(grouping, torch.int32, "grouping"), int(n_groups),
                                 int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                 _dev(result, torch.float64, "result"), sw_ptr,
@@ -281,7 +311,8 @@ def pstat_matrix_register(mat: torch.Tensor, path=PSTAT_PATH_AUTO) -> int:
     p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(mat.device)
     h = _i64(0)
-    _check(_lib.pstat_matrix_register(_dev(mat, torch.float32, "mat"), mat.shape[0], p,
+    mp, n = _mat(mat)
+    _check(_lib.pstat_matrix_register(mp, n, p,
                                       ctypes.byref(h)))
     return int(h.value)
 
@@ -327,7 +358,8 @@ def pstat_job_create(server: int, mat: torch.Tensor, grouping: torch.Tensor, n_g
     p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(mat.device)
     job, units = _i64(0), _i64(0)
-    _check(_lib.pstat_job_create(int(server), _dev(mat, torch.float32, "mat"), mat.shape[0],
+    mp, n = _mat(mat)
+    _check(_lib.pstat_job_create(int(server), mp, n,
                                  _dev(grouping, torch.int32, "grouping"), int(n_groups),
                                  int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF, p,
                                  _dev(scratch, torch.uint8, "scratch"), scratch.numel(),

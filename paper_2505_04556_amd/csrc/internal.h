@@ -19,6 +19,18 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // Number of tiles of an upper-triangular tiling with nt tiles per side.
 inline int64_t tri_count(int64_t nt) { return nt * (nt + 1) / 2; }
 
+// Layouts of D in device memory: the row-major n x n square (packed == 0),
+// or only its strict upper triangle, row after row (packed != 0: row i holds
+// columns i + 1 .. n - 1 and starts at i (2n - i - 1) / 2; n (n - 1) / 2
+// floats in all).  Every kernel reads D only at j > i.
+__host__ __device__ inline int64_t d_row_base(int64_t i, int64_t n, int packed) {
+    // index of element (i, j) = d_row_base(i) + j
+    return packed ? i * (2 * n - i - 1) / 2 - i - 1 : i * n;
+}
+__host__ __device__ inline int64_t d_index(int64_t i, int64_t j, int64_t n, int packed) {
+    return d_row_base(i, n, packed) + j;
+}
+
 // ---- staging (k_stage.hip) ------------------------------------------------
 // int32 [.][n] -> u16 [n_pad][P_pad] (object-major), pads with kPadLabel;
 // staged permutation q is row rows[q] of g (row q when rows is NULL).
@@ -41,7 +53,8 @@ void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_
 // s_T: per-block FP64 partial sums of d^2 over the strict upper triangle,
 // then a fixed-order final sum divided by n.
 int64_t sT_partials_count(int64_t n);
-void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s);
+void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s,
+               int packed = 0);
 // s_T = (sum of count partials, fixed order) / n
 void launch_sT_final(const double *partials, int64_t count, int64_t n, double *sT, hipStream_t s);
 
@@ -64,7 +77,8 @@ constexpr int kServeTile = 32;
 constexpr int kServeLanes = 256;
 struct JobDesc {              // one staged problem, device-resident
     // plain form
-    const float *mat;
+    const float *mat;         // D in the layout `packed` names
+    int32_t packed;
     const uint16_t *lab;      // u16 [n_pad][P_pad], object-major
     const double *w;
     double *partial;          // [chunks][P_pad]
@@ -86,12 +100,13 @@ struct UnitDesc {             // one work-group's share of one job: plain
 // one pass over D: out[q] for q < m.  partial: few_partial_bytes(n, m) bytes.
 size_t few_partial_bytes(int64_t n, int64_t m);
 void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
-                   int32_t k, const double *w, double *partial, double *out, hipStream_t s);
+                   int32_t k, const double *w, double *partial, double *out, hipStream_t s,
+                   int packed = 0);
 // The same with the groupings as u16 rows of `stride` entries (the MFMA
 // forms' staged labels).
 void launch_sw_few_u16(const float *mat, int64_t n, const uint16_t *g, int64_t stride,
                        const int32_t *rows, int64_t m, int32_t k, const double *w, double *partial,
-                       double *out, hipStream_t s);
+                       double *out, hipStream_t s, int packed = 0);
 // out[q] = sum over r < runs, ascending, of partial[r * stride + q], q < m.
 void launch_reduce_partials(const double *partial, int64_t runs, int64_t stride, int64_t m,
                             double *out, hipStream_t s);
@@ -104,7 +119,7 @@ void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int3
 // the label table is permutation q.  f64 selects the FP64 instantiation.
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
                  const uint16_t *lab_om, const double *w, int32_t k, double *partial,
-                 hipStream_t s);
+                 hipStream_t s, int packed = 0);
 
 // ---- MFMA kernels (k_mfma.hip) ---------------------------------------------
 struct MfmaPlan {
@@ -163,7 +178,8 @@ struct PrepassRecheck {
 // stored values.
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
                          double *sT_part = nullptr, double *sT = nullptr,
-                         const PrepassRecheck *rc = nullptr, double *rcs = nullptr);
+                         const PrepassRecheck *rc = nullptr, double *rcs = nullptr,
+                         int packed = 0);
 int64_t prepass_blocks(int64_t n);
 size_t mfma_table_bytes(const MfmaPlan &pl);
 void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                                                  uint4 *__restrict__ tiles,
                                                  double *__restrict__ sT_part, PrepassRecheck rc,
                                                  const uint32_t *__restrict__ f16max,
-                                                 double *__restrict__ rcs) {
+                                                 double *__restrict__ rcs, int packed) {
     constexpr int Q = RC ? kRecheckRows : 1;
     // FP16: the power of two that brings the largest square into [2^14, 2^15)
     float f16sc = 1.0f;
@@ -168,9 +168,12 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                 d[ps][2] = v.z;
                 d[ps][3] = v.w;
             } else {
+                // (the packed layout has no entries at j <= i)
 #pragma unroll
                 for (int e = 0; e < 4; e++)
-                    d[ps][e] = (i < n && j0 + e < n) ? mat[(uint64_t)i * (uint64_t)n + j0 + e] : 0.0f;
+                    d[ps][e] = (i < n && j0 + e < n && (!packed || j0 + e > i))
+                                   ? mat[d_index(i, j0 + e, n, packed)]
+                                   : 0.0f;
             }
         }
         // recheck labels of the unit: thread t loads 8 row labels of grouping
@@ -329,15 +332,16 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
 // into *cell with one atomicMax per work-group.  Work-group b takes rows b,
 // b + gridDim.x, ...
 __global__ __launch_bounds__(256) void k_max_abs_upper(const float *__restrict__ mat, int64_t n,
-                                                       uint32_t *__restrict__ cell) {
+                                                       uint32_t *__restrict__ cell, int packed) {
     __shared__ uint32_t red[4];
     uint32_t m = 0;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t rb = d_row_base(i, n, packed);
         for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
-            const uint32_t b = __builtin_bit_cast(uint32_t, mat[(uint64_t)i * (uint64_t)n + j]) &
-                               0x7FFFFFFFu;
+            const uint32_t b = __builtin_bit_cast(uint32_t, mat[rb + j]) & 0x7FFFFFFFu;
             m = b > m ? b : m;
         }
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         const uint32_t v = (uint32_t)__shfl_xor((int)m, o);
@@ -750,13 +754,15 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
 size_t mfma_table_bytes(const MfmaPlan &pl) { return (size_t)pl.items * 3 * sizeof(int32_t); }
 
 void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hipStream_t s,
-                         double *sT_part, double *sT, const PrepassRecheck *rc, double *rcs) {
+                         double *sT_part, double *sT, const PrepassRecheck *rc, double *rcs,
+                         int packed) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t kb_total = panels * 2;
     const int64_t comp_units = panels * (panels + 1);
     // one s_T partial per work-group: no more work-groups than partial slots
     const int64_t blocks = prepass_blocks(n);
-    const int vec = (n % 4 == 0) && ((uintptr_t)mat % 16 == 0);
+    // 16-byte row reads need 16-byte aligned rows of the square layout
+    const int vec = !packed && (n % 4 == 0) && ((uintptr_t)mat % 16 == 0);
     const dim3 grid((unsigned)blocks);
     uint4 *t = (uint4 *)tiles;
     const PrepassRecheck none{};
@@ -765,11 +771,12 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
         cell = const_cast<uint32_t *>(f16_max_cell(tiles, n));
         launch_fill_i32((int32_t *)cell, 1, 0, s);
         const int64_t mb = n < 2048 ? n : 2048;
-        hipLaunchKernelGGL(k_max_abs_upper, dim3((unsigned)mb), dim3(256), 0, s, mat, n, cell);
+        hipLaunchKernelGGL(k_max_abs_upper, dim3((unsigned)mb), dim3(256), 0, s, mat, n, cell,
+                           packed);
     }
 #define PSTAT_PREPASS(DT_, RC_)                                                                   \
     hipLaunchKernelGGL((k_prepass<DT_, RC_>), grid, dim3(256), 0, s, mat, n, kb_total, comp_units, \
-                       vec, t, sT_part, rc ? *rc : none, cell, rcs)
+                       vec, t, sT_part, rc ? *rc : none, cell, rcs, packed)
     if (rc) {
         if (dtype == 0) PSTAT_PREPASS(0, true);
         else if (dtype == 1) PSTAT_PREPASS(1, true);

@@ -55,7 +55,7 @@ __device__ inline double square<double>(float d) { return (double)d * (double)d;
 // One work unit: tile chunk `chunk` of the triangle for the LANES permutations
 // of group `pg`; writes partial[chunk * P_pad + pg * LANES + lane].
 template <int T, int LANES, typename Acc>
-__device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int64_t nt,
+__device__ inline void plain_unit(const float *__restrict__ mat, int packed, int64_t n, int64_t nt,
                                   int64_t n_tiles, int64_t tiles_per_chunk,
                                   const uint16_t *__restrict__ lab, int64_t P_pad,
                                   const double *__restrict__ w, int32_t k,
@@ -85,7 +85,7 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int6
                 const int r = e / T, c = e % T;
                 const int64_t i = i0 + r, j = j0 + c;
                 float v = 0.0f;
-                if (i < n && j < n && (I_ < J_ || c > r)) v = mat[(uint64_t)i * (uint64_t)n + j];
+                if (i < n && j < n && (I_ < J_ || c > r)) v = mat[d_index(i, j, n, packed)];
                 pre[q] = v;
             }
         };
@@ -168,7 +168,7 @@ __device__ inline int64_t xcd_logical(int64_t bid, int64_t gpad) {
 
 template <int T, int LANES, typename Acc>
 __global__ __launch_bounds__(LANES) void k_plain(
-    const float *__restrict__ mat, int64_t n, int64_t nt, int64_t n_tiles,
+    const float *__restrict__ mat, int packed, int64_t n, int64_t nt, int64_t n_tiles,
     int64_t tiles_per_chunk, int64_t pgroups, int64_t grid_real,
     const uint16_t *__restrict__ lab, int64_t P_pad, const double *__restrict__ w, int32_t k,
     double *__restrict__ partial) {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(LANES) void k_plain(
     if (logical >= grid_real) return;
     __shared__ __align__(16) Acc sD[T][T];
     __shared__ double sWt[kWeightCache];
-    plain_unit<T, LANES, Acc>(mat, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
+    plain_unit<T, LANES, Acc>(mat, packed, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
                               logical / pgroups, logical % pgroups, sD, sWt);
 }
 
@@ -191,19 +191,20 @@ __global__ __launch_bounds__(kServeLanes) void k_plain_worklist(
     const JobDesc j = jobs[u.job];
     __shared__ __align__(16) float sD[kServeTile][kServeTile];
     __shared__ double sWt[kWeightCache];
-    plain_unit<kServeTile, kServeLanes, float>(j.mat, j.n, j.nt, j.n_tiles, j.tiles_per_chunk,
+    plain_unit<kServeTile, kServeLanes, float>(j.mat, j.packed, j.n, j.nt, j.n_tiles,
+                                               j.tiles_per_chunk,
                                                j.lab, j.P_pad, j.w, j.k, j.partial, u.chunk,
                                                u.pgroup, sD, sWt);
 }
 
 template <int T, int LANES, typename Acc>
-void launch_one(const PlainPlan &pl, const float *mat, int64_t n, const uint16_t *lab,
-                const double *w, int32_t k, double *partial, hipStream_t s) {
+void launch_one(const PlainPlan &pl, const float *mat, int packed, int64_t n,
+                const uint16_t *lab, const double *w, int32_t k, double *partial, hipStream_t s) {
     const int64_t grid_real = pl.chunks * pl.pgroups;
     const int64_t gpad = round_up(grid_real, 8);  // xcd_logical needs a multiple of 8
     hipLaunchKernelGGL((k_plain<T, LANES, Acc>), dim3((unsigned)gpad), dim3(LANES), 0, s, mat,
-                       n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups, grid_real, lab,
-                       pl.P_pad, w, k, partial);
+                       packed, n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups, grid_real,
+                       lab, pl.P_pad, w, k, partial);
 }
 
 // ---- few groupings at FP64 (the tie recheck) ---------------------------------
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
                                                 const LT *__restrict__ g, int64_t gstride,
                                                 const int32_t *__restrict__ rows, int64_t m,
                                                 int32_t k, const double *__restrict__ w,
-                                                double *__restrict__ partial, int64_t m_pad) {
+                                                double *__restrict__ partial, int64_t m_pad,
+                                                int packed) {
     static_assert(EQ % 2 == 0, "two groupings per label round");
     constexpr int LR = EQ / 2;   // label loads per thread and tile
     // row labels as [grouping][row % 4][row / 4], so the 16 rows of a thread
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
 #pragma unroll
         for (int u = 0; u < 16; u++) {
             const int64_t i = I * kFT + wave + 4 * u;
-            dn[u] = (j < n && i < j) ? mat[i * n + j] : 0.0f;
+            dn[u] = (j < n && i < j) ? mat[d_index(i, j, n, packed)] : 0.0f;
         }
         const int64_t idx = (side ? J : I) * kFT + c;
 #pragma unroll
@@ -372,12 +374,12 @@ PlainPlan plain_plan(int64_t n, int64_t P, int tile, int lanes, int n_cu) {
 
 int launch_plain(const PlainPlan &pl, bool f64, const float *mat, int64_t n,
                  const uint16_t *lab_om, const double *w, int32_t k, double *partial,
-                 hipStream_t s) {
-#define PSTAT_PLAIN_CASE(T_, L_)                                                         \
-    if (pl.tile == T_ && pl.lanes == L_) {                                               \
-        if (f64) launch_one<T_, L_, double>(pl, mat, n, lab_om, w, k, partial, s);       \
-        else launch_one<T_, L_, float>(pl, mat, n, lab_om, w, k, partial, s);            \
-        return 0;                                                                        \
+                 hipStream_t s, int packed) {
+#define PSTAT_PLAIN_CASE(T_, L_)                                                                 \
+    if (pl.tile == T_ && pl.lanes == L_) {                                                       \
+        if (f64) launch_one<T_, L_, double>(pl, mat, packed, n, lab_om, w, k, partial, s);       \
+        else launch_one<T_, L_, float>(pl, mat, packed, n, lab_om, w, k, partial, s);            \
+        return 0;                                                                                \
     }
     PSTAT_PLAIN_CASE(32, 64)
     PSTAT_PLAIN_CASE(32, 128)
@@ -411,7 +413,8 @@ size_t few_partial_bytes(int64_t n, int64_t m) {
 namespace {
 template <typename LT>
 void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const int32_t *rows,
-              int64_t m, int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
+              int64_t m, int32_t k, const double *w, double *partial, double *out, hipStream_t s,
+              int packed) {
     const int64_t nt = ceil_div(n, kFT);
     const int64_t tiles = nt * (nt + 1) / 2;
     const int64_t runs = tiles < kFewChunks ? tiles : kFewChunks;
@@ -422,17 +425,17 @@ void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const i
         const int64_t m_pad = round_up(mm, 8);
         if (mm <= 4)
             hipLaunchKernelGGL((k_sw_few<4, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
-                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
+                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
         else if (mm <= 8)
             hipLaunchKernelGGL((k_sw_few<8, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
-                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
+                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
         else if (mm <= 12)
             hipLaunchKernelGGL((k_sw_few<12, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat,
-                               n, nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad);
+                               n, nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
         else
             hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
                                dim3(256), 0, s, mat, n, nt, tiles, tpc, g, gstride, rows + b, mm, k,
-                               w, partial, m_pad);
+                               w, partial, m_pad, packed);
         hipLaunchKernelGGL(k_reduce_few, dim3((unsigned)mm), dim3(256), 0, s, partial, used, m_pad,
                            out + b);
     }
@@ -446,14 +449,15 @@ void launch_reduce_partials(const double *partial, int64_t runs, int64_t stride,
 }
 
 void launch_sw_few(const float *mat, int64_t n, const int32_t *g, const int32_t *rows, int64_t m,
-                   int32_t k, const double *w, double *partial, double *out, hipStream_t s) {
-    sw_few_t(mat, n, g, n, rows, m, k, w, partial, out, s);
+                   int32_t k, const double *w, double *partial, double *out, hipStream_t s,
+                   int packed) {
+    sw_few_t(mat, n, g, n, rows, m, k, w, partial, out, s, packed);
 }
 
 void launch_sw_few_u16(const float *mat, int64_t n, const uint16_t *g, int64_t stride,
                        const int32_t *rows, int64_t m, int32_t k, const double *w, double *partial,
-                       double *out, hipStream_t s) {
-    sw_few_t(mat, n, g, stride, rows, m, k, w, partial, out, s);
+                       double *out, hipStream_t s, int packed) {
+    sw_few_t(mat, n, g, stride, rows, m, k, w, partial, out, s, packed);
 }
 
 } // namespace pstat

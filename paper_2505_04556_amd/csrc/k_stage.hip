@@ -165,12 +165,12 @@ constexpr int kSTBlocks = 2048;
 // Block b sums rows b, b + G, b + 2G, ...; each row's strict-upper part is
 // strided over the 256 threads; fixed-shape tree reduction in LDS.
 __global__ __launch_bounds__(256) void k_sT_partial(const float *__restrict__ mat, int64_t n,
-                                                    double *__restrict__ partials) {
+                                                    double *__restrict__ partials, int packed) {
     double acc = 0.0;
     for (int64_t i = blockIdx.x; i < n - 1; i += gridDim.x) {
-        const float *row = mat + (uint64_t)i * (uint64_t)n;
+        const int64_t rb = d_row_base(i, n, packed);
         for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
-            const double d = (double)row[j];
+            const double d = (double)mat[rb + j];
             acc += d * d;
         }
     }
@@ -260,9 +260,11 @@ void launch_group_weights(const int32_t *grouping, int64_t n, int32_t k, uint32_
 
 int64_t sT_partials_count(int64_t n) { return n - 1 < kSTBlocks ? (n > 1 ? n - 1 : 1) : kSTBlocks; }
 
-void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s) {
+void launch_sT(const float *mat, int64_t n, double *partials, double *sT, hipStream_t s,
+               int packed) {
     const int64_t blocks = sT_partials_count(n);
-    hipLaunchKernelGGL(k_sT_partial, dim3((unsigned)blocks), dim3(256), 0, s, mat, n, partials);
+    hipLaunchKernelGGL(k_sT_partial, dim3((unsigned)blocks), dim3(256), 0, s, mat, n, partials,
+                       packed);
     hipLaunchKernelGGL(k_sT_final, dim3(1), dim3(256), 0, s, partials, blocks, n, sT);
 }
 

@@ -26,6 +26,7 @@ struct Registered {
     int path;
     int device;
     void *tiles;
+    int packed;   // layout of mat
 };
 std::map<int64_t, Registered> g_registered;
 int64_t g_next_handle = 1;
@@ -201,7 +202,7 @@ size_t sW_bytes(int64_t n, int64_t P, int32_t k, int path, bool own_tiles, bool 
 int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
             double *out, const void *tiles, int32_t *err_flag, bool timed, double *sT_part,
-            double *sT, bool staged, const PrepassRecheck *samples) {
+            double *sT, bool staged, const PrepassRecheck *samples, int packed) {
     hipStream_t s = tls.stream;
     int rc;
     if (!staged) launch_fill_u8(L.bad, P, 0, s);
@@ -210,7 +211,8 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
                                err_flag, s);
         if ((rc = check_launch("label staging"))) return rc;
         KernelTimer timer(s, timed);
-        if (launch_plain(L.pp, L.path == PSTAT_PATH_PLAIN_F64, mat, n, L.lab, w, k, L.partial, s))
+        if (launch_plain(L.pp, L.path == PSTAT_PATH_PLAIN_F64, mat, n, L.lab, w, k, L.partial, s,
+                         packed))
             return fail(PSTAT_EINVAL, "no plain kernel for tile %d, lanes %d", L.pp.tile,
                         L.pp.lanes);
         timer.stop(s);
@@ -226,7 +228,7 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
     if (L.mp.cx && tiles) return fail(PSTAT_EINVAL, "complement form needs the pre-pass");
     if (!tiles) {
         launch_mfma_prepass(mat, n, L.mp.dtype, L.tiles, s, sT_part, sT, samples,
-                            L.mp.cx ? L.cx.rcs : nullptr);
+                            L.mp.cx ? L.cx.rcs : nullptr, packed);
         if ((rc = check_launch("mfma prepass"))) return rc;
         tiles = L.tiles;
     }
@@ -264,7 +266,7 @@ int scan_labels_sync(const int32_t *g, int64_t count, int32_t limit, int32_t *ma
 
 int sW_common(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
               int32_t n_groups, const double *w, double *out, bool validate_sync,
-              const void *tiles, int path) {
+              const void *tiles, int path, int packed) {
     int rc = need_init();
     if (rc) return rc;
     if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2 (got %lld)", (long long)n);
@@ -289,7 +291,8 @@ int sW_common(const float *mat, int64_t n, const int32_t *groupings, int64_t n_p
     Carver c{ws, need, 0, false};
     SwLayout L;
     layout_sW(c, n, n_perms, k, path, tiles == nullptr, L);
-    return exec_sW(L, mat, n, groupings, nullptr, n_perms, k, k, w, out, tiles, tls.flags);
+    return exec_sW(L, mat, n, groupings, nullptr, n_perms, k, k, w, out, tiles, tls.flags, true,
+                   nullptr, nullptr, false, nullptr, packed);
 }
 
 int init_flags() {
@@ -333,12 +336,13 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked_out,
-                bool sT_ready, const uint16_t *lab16, int64_t stride16, bool samples_ready) {
+                bool sT_ready, const uint16_t *lab16, int64_t stride16, bool samples_ready,
+                int packed) {
     hipStream_t s = tls.stream;
     int rc;
     const int64_t R = n_perms + 1;
     if (!sT_ready) {
-        launch_sT(mat, n, h.sTp, h.sT, s);
+        launch_sT(mat, n, h.sTp, h.sT, s, packed);
         if ((rc = check_launch("s_T"))) return rc;
     }
     // FP64 recheck.  First the observed grouping and the first few
@@ -354,9 +358,10 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
         // FP64 s_W of the groupings listed in h.list[0..m)
         auto recheck = [&](int64_t m) {
             if (lab16)
-                launch_sw_few_u16(mat, n, lab16, stride16, h.list, m, k, h.w, partial, h.vals, s);
+                launch_sw_few_u16(mat, n, lab16, stride16, h.list, m, k, h.w, partial, h.vals, s,
+                                  packed);
             else
-                launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s);
+                launch_sw_few(mat, n, h.allg, h.list, m, k, h.w, partial, h.vals, s, packed);
         };
         launch_iota(h.list, S, s);
         if (!samples_ready) recheck(S);
@@ -429,6 +434,13 @@ int pstat_init(int device) {
     return init_flags();
 }
 
+int pstat_set_matrix_layout(int layout) {
+    if (layout != PSTAT_LAYOUT_SQUARE && layout != PSTAT_LAYOUT_UPPER_PACKED)
+        return fail(PSTAT_EINVAL, "unknown matrix layout %d", layout);
+    tls.packed = layout == PSTAT_LAYOUT_UPPER_PACKED;
+    return PSTAT_OK;
+}
+
 int pstat_set_stream(void *hip_stream) {
     tls.stream = (hipStream_t)hip_stream;
     return PSTAT_OK;
@@ -485,13 +497,14 @@ size_t pstat_workspace_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int p
 
 int pstat_sW(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
              const double *inv_group_sizes, double *out) {
-    return sW_common(mat, n, groupings, n_perms, 0, inv_group_sizes, out, true, nullptr, tls.path);
+    return sW_common(mat, n, groupings, n_perms, 0, inv_group_sizes, out, true, nullptr, tls.path,
+                     tls.packed);
 }
 
 int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
                int32_t n_groups, const double *inv_group_sizes, double *out) {
     return sW_common(mat, n, groupings, n_perms, n_groups, inv_group_sizes, out, false, nullptr,
-                     tls.path);
+                     tls.path, tls.packed);
 }
 
 int pstat_check_labels(void) {
@@ -516,7 +529,7 @@ int pstat_sT(const float *mat, int64_t n, double *s_T) {
     char *ws;
     const size_t need = (size_t)sT_partials_count(n) * sizeof(double) + 256;
     if ((rc = acquire_workspace(need, &ws))) return rc;
-    launch_sT(mat, n, (double *)ws, s_T, tls.stream);
+    launch_sT(mat, n, (double *)ws, s_T, tls.stream, tls.packed);
     return check_launch("s_T");
 }
 
@@ -647,11 +660,11 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         prc.out = h.vals;
     }
     if ((rc = exec_sW(L, mat, n, h.allg, nullptr, R, k, k, h.w, h.sw, nullptr, tls.flags, true,
-                      h.sTp, h.sT, staged, mf ? &prc : nullptr)))
+                      h.sTp, h.sT, staged, mf ? &prc : nullptr, tls.packed)))
         return rc;
     int64_t rechecked = 0;
     if ((rc = finish_test(h, mat, n, k, n_perms, path, ws + head + swb, fpb, &rechecked, mf,
-                          staged ? L.lab : nullptr, L.mp.n_pad, mf)))
+                          staged ? L.lab : nullptr, L.mp.n_pad, mf, tls.packed)))
         return rc;
     if (n_rechecked) *n_rechecked = rechecked;
     return PSTAT_OK;
@@ -668,7 +681,8 @@ int pstat_matrix_register(const float *mat, int64_t n, int path, int64_t *handle
     void *tiles = nullptr;
     if (is_mfma(path)) {
         HIP_TRY(hipMalloc(&tiles, mfma_tile_bytes(n, mfma_dtype(path))));
-        launch_mfma_prepass(mat, n, mfma_dtype(path), tiles, tls.stream);
+        launch_mfma_prepass(mat, n, mfma_dtype(path), tiles, tls.stream, nullptr, nullptr,
+                            nullptr, nullptr, tls.packed);
         if ((rc = check_launch("mfma prepass"))) {
             (void)hipFree(tiles);
             return rc;
@@ -676,7 +690,7 @@ int pstat_matrix_register(const float *mat, int64_t n, int path, int64_t *handle
     }
     std::lock_guard<std::mutex> lk(g_mu);
     const int64_t h = g_next_handle++;
-    g_registered[h] = Registered{mat, n, path, tls.device, tiles};
+    g_registered[h] = Registered{mat, n, path, tls.device, tiles, tls.packed};
     *handle = h;
     return PSTAT_OK;
 }
@@ -709,7 +723,7 @@ int pstat_sW_registered(int64_t handle, const int32_t *groupings, int64_t n_perm
     }
     if (r.device != tls.device) return fail(PSTAT_EINVAL, "handle belongs to device %d", r.device);
     return sW_common(r.mat, r.n, groupings, n_perms, n_groups, inv_group_sizes, out, false,
-                     r.tiles, r.path);
+                     r.tiles, r.path, r.packed);
 }
 
 int pstat_profile(int on) {

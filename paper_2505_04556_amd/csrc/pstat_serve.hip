@@ -21,6 +21,7 @@ struct Job {
     int kind = 0;                  // 0 plain FP32, 1 MFMA split BF16 (512-column
                                    // work-groups), 2 the same with 256 columns
     const float *mat = nullptr;
+    int packed = 0;                // layout of mat
     int64_t n = 0, n_perms = 0;
     int32_t k = 0;
     TestHead head{};
@@ -255,6 +256,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     JobDesc &d = sv->jobs_host[slot];
     memset(&d, 0, sizeof(JobDesc));
     d.mat = mat;
+    d.packed = tls.packed;
     d.w = L.head.w;
     d.n = n;
     d.k = n_groups;
@@ -284,7 +286,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
         prc.out = L.head.vals;
         if (L.mp.cx) launch_largest_group(L.head.counts, n_groups, L.cx.L, s);
         launch_mfma_prepass(mat, n, 2, L.tiles, s, L.head.sTp, L.head.sT, &prc,
-                            L.mp.cx ? L.cx.rcs : nullptr);
+                            L.mp.cx ? L.cx.rcs : nullptr, tls.packed);
         if (L.mp.cx) {
             launch_complement_sums(L.cx, n, s);
             launch_vnot(L.cx, L.lab, L.mp.n_pad, n, R, s);
@@ -307,6 +309,7 @@ int pstat_job_create(int64_t server, const float *mat, int64_t n, const int32_t 
     J.live = true;
     J.kind = kind;
     J.mat = mat;
+    J.packed = tls.packed;
     J.n = n;
     J.n_perms = n_perms;
     J.k = n_groups;
@@ -420,7 +423,7 @@ int pstat_job_finish(int64_t server, int64_t job, double *result, double *sW_all
     int64_t rechecked = 0;
     if ((rc = finish_test(J.head, J.mat, J.n, J.k, J.n_perms,
                           J.kind == 0 ? PSTAT_PATH_PLAIN_F32 : PSTAT_PATH_MFMA_SPLIT_BF16, ws, region,
-                          &rechecked, J.kind != 0, nullptr, 0, J.kind != 0)))
+                          &rechecked, J.kind != 0, nullptr, 0, J.kind != 0, J.packed)))
         return rc;
     if (sW_all)
         HIP_TRY(hipMemcpyAsync(sW_all, J.head.sw, (size_t)R * sizeof(double),

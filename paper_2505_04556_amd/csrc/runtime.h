@@ -30,6 +30,7 @@ struct Thread {
     int device = -1;
     hipStream_t stream = nullptr;
     int path = PSTAT_PATH_AUTO;
+    int packed = 0;   // layout of the matrices passed on this thread (PSTAT_LAYOUT_*)
     Tuning tuning[PSTAT_N_PATHS];
     void *ws_user = nullptr;
     size_t ws_user_bytes = 0;
@@ -130,7 +131,7 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
             const int32_t *rows, int64_t P, int32_t k, int32_t limit, const double *w,
             double *out, const void *tiles, int32_t *err_flag, bool timed = true,
             double *sT_part = nullptr, double *sT = nullptr, bool staged = false,
-            const PrepassRecheck *samples = nullptr);
+            const PrepassRecheck *samples = nullptr, int packed = 0);
 int scan_labels_sync(const int32_t *g, int64_t count, int32_t limit, int32_t *max_label);
 
 // ---- the whole permutation test in phases ------------------------------------
@@ -166,7 +167,7 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
 int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64_t n_perms,
                 int path, char *region, size_t region_bytes, int64_t *rechecked,
                 bool sT_ready = false, const uint16_t *lab16 = nullptr, int64_t stride16 = 0,
-                bool samples_ready = false);
+                bool samples_ready = false, int packed = 0);
 
 // Tie band of the p-value recheck: kBandMargin times the largest relative
 // error of the fast path over the observed grouping and the first

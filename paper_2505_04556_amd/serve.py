@@ -39,7 +39,9 @@ class Request:
     n_perms: int
     seed: int
     arrival: float = 0.0            # seconds after the trace starts
-    make_matrix: Callable | None = None   # device -> float32 [n, n] tensor
+    make_matrix: Callable | None = None   # device -> float32 [n, n] tensor, or the
+                                          # packed strict upper triangle [n (n - 1) / 2]
+    packed: bool = False            # make_matrix returns the packed layout
 
     @property
     def pair_perms(self) -> int:
@@ -101,8 +103,8 @@ class GpuExecutor(Executor):
 
     def footprint(self, req: Request) -> int:
         ps = self.ps
-        return (4 * req.n * req.n + ps.pstat_job_bytes(req.n, req.n_perms, req.k, self.path)
-                + 4 * req.n)
+        mat = 2 * req.n * (req.n - 1) if req.packed else 4 * req.n * req.n
+        return mat + ps.pstat_job_bytes(req.n, req.n_perms, req.k, self.path) + 4 * req.n
 
     def form(self, req: Request) -> str:
         return self.ps.resolve_path(self.path, req.n, req.k)

@@ -63,3 +63,12 @@ def test_binding_names_match_header():
     except ImportError:
         pytest.skip("library not built")
     assert sorted(mod.exported_symbols()) == declared_symbols()
+
+
+def test_packed_n():
+    import paper_2505_04556_amd as ps
+    for n in (2, 3, 10, 1000, 380_000):
+        assert ps.packed_n(n * (n - 1) // 2) == n
+    for bad in (0, 2, 4, 5, 4949):
+        with pytest.raises(ps.PstatError):
+            ps.packed_n(bad)

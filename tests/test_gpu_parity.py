@@ -576,3 +576,58 @@ def test_two_threads_on_their_own_streams(ps):
     for i in range(2):
         assert np.array_equal(alone[i][0], both[i][0])
         assert np.array_equal(alone[i][1], both[i][1])
+
+
+# --- the packed strict-upper-triangle layout ----------------------------------
+def packed(D):
+    """The strict upper triangle of a square device tensor, row after row."""
+    import torch
+    n = D.shape[0]
+    iu = torch.triu_indices(n, n, 1, device=D.device)
+    return D[iu[0], iu[1]].contiguous()
+
+
+# Only addresses change: every form gives the same bits from either layout.
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("n,sizes,P", [(2, [2], 3), (257, [57, 100, 100], 129),
+                                       (1000, [100, 200, 300, 400], 300)])
+def test_packed_layout_bit_identical(ps, path, n, sizes, P):
+    import torch
+    D, base, perms, w = problem(n, sizes, P, mseed=n + 1, pseed=P + 1)
+    Dd, gd, wd = to_dev(D, perms, w)
+    ps.pstat_set_path(path)
+    a = ps.pstat_sW(Dd, gd, wd).cpu().numpy()
+    b = ps.pstat_sW(packed(Dd), gd, wd).cpu().numpy()
+    ps.pstat_set_path("auto")
+    assert np.array_equal(a, b)
+    assert max_rel(b, oracle.sW(D, perms, w)) <= TOL[path]
+    assert ps.pstat_sT(Dd).item() == ps.pstat_sT(packed(Dd)).item()
+
+
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16", "mfma_f16"])
+def test_packed_layout_whole_test(ps, path):
+    import torch
+    sizes = [300, 450, 250]
+    n, k, P, seed = sum(sizes), len(sizes), 999, 4
+    D = synth.uniform_matrix(n, 17)
+    base = synth.base_labels(sizes)
+    Dd, bd = to_dev(D, base)
+    ps.pstat_set_path(path)
+    out = []
+    for M in (Dd, packed(Dd)):
+        sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+        res, rechecked = ps.pstat_permanova(M, bd, k, P, seed, sW_all=sw)
+        out.append((res.cpu().numpy(), sw.cpu().numpy(), rechecked))
+    # a registered matrix in the packed layout
+    h = ps.pstat_matrix_register(packed(Dd), path)
+    rows = to_dev(np.vstack([base, oracle.permute(base, 20, 3)]))[0]
+    wd = to_dev(synth.inv_group_sizes(sizes))[0]
+    reg = ps.pstat_sW_registered(h, rows, k, wd).cpu().numpy()
+    ps.pstat_matrix_release(h)
+    direct = ps.pstat_sW_k(Dd, rows, k, wd).cpu().numpy()
+    ps.pstat_set_path("auto")
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+    assert np.array_equal(reg, direct)
+    ref = oracle.permanova(D, base, P, seed)
+    assert out[1][0][1] == ref["p"]

@@ -141,3 +141,26 @@ def test_serving_trace_matches_oracle_on_a_subset(ps):
         assert o.result[1] == ref["p"], t["id"]
         checked += 1
     assert checked >= 16
+
+
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16"])
+def test_packed_matrix_jobs_equal_square(ps, path):
+    # the same requests with D given as its packed strict upper triangle
+    import torch
+    from paper_2505_04556_amd.serve import Request
+
+    def pack(D):
+        iu = torch.triu_indices(D.shape[0], D.shape[0], 1, device=D.device)
+        return D[iu[0], iu[1]].contiguous()
+
+    reqs = requests()[:4]
+    square, _ = serve(reqs, path=path, round_work=4e6)
+    preqs = [Request(id=r.id, n=r.n, k=r.k, grouping=r.grouping, n_perms=r.n_perms, seed=r.seed,
+                     arrival=0.0, packed=True,
+                     make_matrix=(lambda dev, r=r: pack(r.make_matrix(dev))))
+             for r in reqs]
+    packed, _ = serve(preqs, path=path, round_work=4e6)
+    for r in reqs:
+        a, b = square["outcomes"][r.id], packed["outcomes"][r.id]
+        assert a.result == b.result, r.id
+        assert np.array_equal(a.sW_all, b.sW_all), r.id
