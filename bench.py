@@ -127,6 +127,31 @@ def speedup_leg(ps, torch, sd, synth, steps=3, warmup=1):
                                    "(every permutation against the FP64 oracle)")
 
 
+def packed_leg(ps, torch, sd, synth, n, steps=2, warmup=1):
+    """The whole test with D given as its packed strict upper triangle (half
+    the memory of the square): hash-uniform distances, k = 3 groups of 20/30/50%
+    of n, 999 permutations, split BF16 -- the n = 100,000 workload's shape at
+    any n, up to sizes whose square layout would not fit beside the tiles."""
+    sizes = [n // 5, 3 * n // 10]
+    sizes.append(n - sum(sizes))
+    cfg = dict(n=n, k=3, n_perms=999, perm_seed=3003, sizes=sizes)
+    torch.cuda.empty_cache()
+    D = sd.uniform_packed(n, 1001)
+    base = torch.from_numpy(synth.base_labels(sizes)).cuda()
+    r = time_path(ps, torch, "mfma_split_bf16", D, base, cfg, steps, warmup)
+    ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
+    del D
+    ps.pstat_free_workspace()
+    torch.cuda.empty_cache()
+    pair_perms = n * (n - 1) // 2 * cfg["n_perms"]
+    return dict(workload=f"n{n}_k3_P999_uniform_packed", layout="strict upper triangle, packed",
+                matrix_GB=round(2 * n * (n - 1) / 1e9, 1), steps=steps,
+                ms_per_step=round(r["ms_per_step"], 3),
+                kernel_ms=round(r["kernel_ms_total"] / max(1, r["kernel_launches"]), 3),
+                G_pair_perms_per_s=round(pair_perms / (r["ms_per_step"] / 1e3) / 1e9, 1),
+                F_obs=float(r["result"][0]), p=float(r["result"][1]), rechecked=r["rechecked"])
+
+
 def cpu_baseline(D_host, cfg, target_s=12.0):
     """The FP64 oracle, as it stands, on this host's cores over a bounded
     sample of the same workload's permutations."""
@@ -277,6 +302,8 @@ def main() -> int:
     ap.add_argument("--serve-seeds", type=int, default=1,
                     help="replay the serving trace under this many arrival seeds and pool "
                          "the latencies")
+    ap.add_argument("--packed-n", type=int, default=0,
+                    help="also time a whole test of this n with D in the packed layout")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -347,6 +374,12 @@ def main() -> int:
         log("vendor BF16 GEMM rate (torch.matmul) for context")
         gemm = gemm_ceiling(torch)
         log(f"  {gemm}")
+
+    packed = None
+    if args.packed_n:
+        log(f"packed-layout leg: n={args.packed_n:,}, k=3, 999 permutations, split BF16")
+        packed = packed_leg(ps, torch, sd, synth, args.packed_n)
+        log(f"  {packed}")
 
     serve = None
     if not args.no_serve:
@@ -449,6 +482,8 @@ def main() -> int:
                                                  if roof["bound"] == "mfma" else None)}
     if speedup is not None:
         out["speedup_n25000"] = speedup
+    if packed is not None:
+        out["packed_leg"] = packed
     if serve is not None:
         out["serve"] = serve
     if cpu is not None:

@@ -111,6 +111,12 @@ int pstat_set_tuning(int path, int tile, int batch);
 /* Caller-owned device workspace for this thread (NULL, 0 = library-managed). */
 int pstat_set_workspace(void *dev_ptr, size_t bytes);
 
+/* Free the library-managed workspace of this thread (after the device's
+ * queued work has finished); the next call that needs one allocates it
+ * again.  For callers that alternate very large problems with other device
+ * work.  PSTAT_OK when there is none. */
+int pstat_free_workspace(void);
+
 /* Workspace pstat_sW_k needs for this shape and path (bytes), 0 on bad input. */
 size_t pstat_workspace_bytes(int64_t n, int64_t n_perms, int32_t n_groups, int path);
 

@@ -76,6 +76,7 @@ _SIGS = {
     "pstat_init": ([_int], _int),
     "pstat_set_stream": ([_P], _int),
     "pstat_set_matrix_layout": ([_int], _int),
+    "pstat_free_workspace": ([], _int),
     "pstat_set_path": ([_int], _int),
     "pstat_set_tuning": ([_int, _int, _int], _int),
     "pstat_set_workspace": ([_P, _size], _int),
@@ -194,6 +195,11 @@ def pstat_set_workspace(ws: torch.Tensor | None) -> None:
         return
     _ready(ws.device)
     _check(_lib.pstat_set_workspace(_dev(ws, torch.uint8, "workspace"), ws.numel()))
+
+
+def pstat_free_workspace() -> None:
+    """Return the library-managed workspace of this thread to the device."""
+    _check(_lib.pstat_free_workspace())
 
 
 def pstat_workspace_bytes(n: int, n_perms: int, n_groups: int, path=PSTAT_PATH_AUTO) -> int:

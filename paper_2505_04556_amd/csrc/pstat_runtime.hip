@@ -477,6 +477,22 @@ int pstat_set_tuning(int path, int tile, int batch) {
     return PSTAT_OK;
 }
 
+int pstat_free_workspace(void) {
+    if (!tls.ws_own) return PSTAT_OK;
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    HIP_TRY(hipSetDevice(tls.ws_own_device));
+    // work queued on any stream of that device may still read it
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(tls.ws_own);
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "freeing the library workspace");
+    tls.ws_own = nullptr;
+    tls.ws_own_bytes = 0;
+    tls.ws_own_device = -1;
+    return PSTAT_OK;
+}
+
 int pstat_set_workspace(void *dev_ptr, size_t bytes) {
     if (dev_ptr) {
         int rc = need_init();

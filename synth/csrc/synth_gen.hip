@@ -36,6 +36,20 @@ __global__ void k_uniform(float *__restrict__ out, int64_t n, int64_t row0, int6
     }
 }
 
+// The same values, strict upper triangle only, packed row after row (row i
+// holds columns i + 1 .. n - 1 from element i (2n - i - 1) / 2 on).
+__global__ void k_uniform_packed(float *__restrict__ out, int64_t n, uint64_t seed_mix) {
+    for (int64_t i = blockIdx.y; i < n - 1; i += gridDim.y) {
+        const int64_t base = i * (2 * n - i - 1) / 2 - i - 1;
+        for (int64_t j = i + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+             j += (int64_t)gridDim.x * blockDim.x) {
+            const uint64_t h = mix64(((uint64_t)i * (uint64_t)n + (uint64_t)j) ^ seed_mix);
+            const uint64_t m = ((h >> 41) << 1) | 1ull;
+            out[base + j] = (float)((double)m * 0x1p-24);
+        }
+    }
+}
+
 __device__ inline double pair_dist(const double *__restrict__ x, int64_t i, int64_t j, int dims) {
     double acc = 0.0;
     for (int d = 0; d < dims; d++) {
@@ -83,6 +97,15 @@ int synth_uniform(float *out, int64_t n, int64_t row0, int64_t rows, uint64_t se
     dim3 grid((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64),
               (unsigned)(rows < 4096 ? rows : 4096));
     hipLaunchKernelGGL(k_uniform, grid, dim3(256), 0, (hipStream_t)stream, out, n, row0, rows,
+                       seed_mix);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// the uniform matrix's strict upper triangle, packed: n (n - 1) / 2 floats
+int synth_uniform_packed(float *out, int64_t n, uint64_t seed_mix, void *stream) {
+    dim3 grid((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64),
+              (unsigned)(n < 8192 ? n : 8192));
+    hipLaunchKernelGGL(k_uniform_packed, grid, dim3(256), 0, (hipStream_t)stream, out, n,
                        seed_mix);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

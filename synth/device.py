@@ -23,6 +23,8 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(_LIB_PATH)
         L.synth_uniform.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p]
+        L.synth_uniform_packed.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                                           ctypes.c_void_p]
         L.synth_euclid.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
@@ -45,6 +47,16 @@ def uniform_matrix(n: int, seed: int, device="cuda", out: torch.Tensor | None = 
                              _stream(out.device))
     if rc != 0:
         raise RuntimeError("synth_uniform launch failed")
+    return out
+
+
+def uniform_packed(n: int, seed: int, device="cuda") -> torch.Tensor:
+    """The hash-uniform matrix's strict upper triangle, packed row after row
+    (n (n - 1) / 2 floats), on the device; equal to the square's entries."""
+    out = torch.empty(n * (n - 1) // 2, dtype=torch.float32, device=device)
+    rc = lib().synth_uniform_packed(out.data_ptr(), n, synth.mix64(int(seed)), _stream(out.device))
+    if rc != 0:
+        raise RuntimeError("synth_uniform_packed launch failed")
     return out
 
 

@@ -10,6 +10,8 @@
 * n = 100,000 (40 GB matrix, k = 3, 999 permutations): 64-bit offsets; sampled
   permutations against the oracle fed by row blocks copied from the device,
   F_obs against the oracle, and the p-value consistent with the returned s_W.
+* n = 229,376 in the packed layout (only the strict upper triangle): a size
+  whose square layout would not fit beside the MFMA tiles; closed form.
 """
 import json
 import os
@@ -183,3 +185,41 @@ def test_n100000_sampled(ps):
         # p is the count of the returned s_W at or below the observed one
         assert res[1] == (1 + np.sum(sw[1:] <= sw[0])) / (1 + P)
     record("n100000", dict(sample=sample, F_obs=F_obs, forms=out))
+
+
+def test_n229376_packed_closed_form(ps):
+    """n = 229,376 in the packed layout: D (105 GB) and the split-BF16 tiles
+    (105 GB) fit on the device together, where the square layout (210 GB) and
+    its tiles would not.  Constant distances d = 1/2 make every s_W the closed
+    form (1/8)(n - k) (each group contributes (n_g - 1) / 8); power-of-two
+    group sizes make the weights exact, so every sum, the FP64 recheck's
+    included, is exact: s_T = (1/8)(n - 1), F = 1 and p = 1."""
+    import torch
+    torch.cuda.empty_cache()
+    ps.pstat_free_workspace()
+    sizes, P, seed = [32_768, 65_536, 131_072], 99, 5
+    n = sum(sizes)
+    k = len(sizes)
+    free, _ = torch.cuda.mem_get_info()
+    need = 4 * n * n + (8 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB free, {free / 1e9:.0f} GB are")
+    D = torch.full((n * (n - 1) // 2,), 0.5, dtype=torch.float32, device="cuda")
+    base = torch.from_numpy(synth.base_labels(sizes)).cuda()
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    ps.pstat_set_path("mfma_split_bf16")
+    try:
+        t0 = time.time()
+        res, rech = ps.pstat_permanova(D, base, k, P, seed, sW_all=sw)
+        torch.cuda.synchronize()
+        seconds = time.time() - t0
+    finally:
+        ps.pstat_set_path("auto")
+        del D
+        ps.pstat_free_workspace()
+        torch.cuda.empty_cache()
+    sw, res = sw.cpu().numpy(), res.cpu().numpy()
+    record("n229376_packed", dict(seconds_first_call=seconds, rechecked=rech, result=list(res)))
+    assert np.all(sw == 0.125 * (n - k))
+    assert res[0] == 1.0 and res[1] == 1.0
+    assert res[3] == 0.125 * (n - 1)

@@ -631,3 +631,11 @@ def test_packed_layout_whole_test(ps, path):
     assert np.array_equal(reg, direct)
     ref = oracle.permanova(D, base, P, seed)
     assert out[1][0][1] == ref["p"]
+
+
+def test_device_packed_generator_matches_square(ps):
+    import synth.device as sd
+    for n in (2, 3, 300):
+        a = sd.uniform_packed(n, 77).cpu().numpy()
+        b = packed(sd.uniform_matrix(n, 77)).cpu().numpy()
+        assert np.array_equal(a, b)
