@@ -428,7 +428,7 @@ def main() -> int:
                                        "profiles/k_plain_f32_n10000_hbm_traffic.txt")
         roof = dict(bound="alu", achieved=round(achieved, 2), peak=round(PEAK_VALU_TOPS, 2),
                     unit="TFLOP/s", frac=round(achieved / PEAK_VALU_TOPS, 4), traffic=traffic,
-                    kernel="k_plain<32,256,float>", kernel_ms=round(kern_ms, 4),
+                    kernel="k_plain<32,256,float,false>", kernel_ms=round(kern_ms, 4),
                     work_per_launch=f"{PLAIN_OPS_PER_PAIRPERM} VALU lane-ops x {pairs} pairs x "
                                     f"{R} groupings")
 

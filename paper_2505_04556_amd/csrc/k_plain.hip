@@ -53,9 +53,11 @@ template <>
 __device__ inline double square<double>(float d) { return (double)d * (double)d; }
 
 // One work unit: tile chunk `chunk` of the triangle for the LANES permutations
-// of group `pg`; writes partial[chunk * P_pad + pg * LANES + lane].
-template <int T, int LANES, typename Acc>
-__device__ inline void plain_unit(const float *__restrict__ mat, int packed, int64_t n, int64_t nt,
+// of group `pg`; writes partial[chunk * P_pad + pg * LANES + lane].  PK: D in
+// the packed layout (a separate instantiation, so the square one keeps its
+// plain row-major addressing).
+template <int T, int LANES, typename Acc, bool PK>
+__device__ inline void plain_unit(const float *__restrict__ mat, int64_t n, int64_t nt,
                                   int64_t n_tiles, int64_t tiles_per_chunk,
                                   const uint16_t *__restrict__ lab, int64_t P_pad,
                                   const double *__restrict__ w, int32_t k,
@@ -79,14 +81,20 @@ __device__ inline void plain_unit(const float *__restrict__ mat, int packed, int
         float pre[kPer];
         auto fetch = [&](int64_t I_, int64_t J_) {
             const int64_t i0 = I_ * T, j0 = J_ * T;
+            // packed: the row base of this thread's first row, then stepped
+            // by LANES / T rows (d_row_base(i + 1) = d_row_base(i) + n - i - 2)
+            constexpr int S = LANES / T;
+            int64_t rb = PK ? d_row_base(i0 + tid / T, n, 1) : 0;
 #pragma unroll
             for (int q = 0; q < kPer; q++) {
                 const int e = tid + q * LANES;
                 const int r = e / T, c = e % T;
                 const int64_t i = i0 + r, j = j0 + c;
                 float v = 0.0f;
-                if (i < n && j < n && (I_ < J_ || c > r)) v = mat[d_index(i, j, n, packed)];
+                if (i < n && j < n && (I_ < J_ || c > r))
+                    v = PK ? mat[rb + j] : mat[(uint64_t)i * (uint64_t)n + j];
                 pre[q] = v;
+                if (PK) rb += S * (n - i - 2) - S * (S - 1) / 2;
             }
         };
         fetch(I, J);
@@ -166,9 +174,9 @@ __device__ inline int64_t xcd_logical(int64_t bid, int64_t gpad) {
     return (bid & 7) * (gpad >> 3) + (bid >> 3);
 }
 
-template <int T, int LANES, typename Acc>
+template <int T, int LANES, typename Acc, bool PK>
 __global__ __launch_bounds__(LANES) void k_plain(
-    const float *__restrict__ mat, int packed, int64_t n, int64_t nt, int64_t n_tiles,
+    const float *__restrict__ mat, int64_t n, int64_t nt, int64_t n_tiles,
     int64_t tiles_per_chunk, int64_t pgroups, int64_t grid_real,
     const uint16_t *__restrict__ lab, int64_t P_pad, const double *__restrict__ w, int32_t k,
     double *__restrict__ partial) {
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(LANES) void k_plain(
     if (logical >= grid_real) return;
     __shared__ __align__(16) Acc sD[T][T];
     __shared__ double sWt[kWeightCache];
-    plain_unit<T, LANES, Acc>(mat, packed, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
+    plain_unit<T, LANES, Acc, PK>(mat, n, nt, n_tiles, tiles_per_chunk, lab, P_pad, w, k, partial,
                               logical / pgroups, logical % pgroups, sD, sWt);
 }
 
@@ -191,10 +199,16 @@ __global__ __launch_bounds__(kServeLanes) void k_plain_worklist(
     const JobDesc j = jobs[u.job];
     __shared__ __align__(16) float sD[kServeTile][kServeTile];
     __shared__ double sWt[kWeightCache];
-    plain_unit<kServeTile, kServeLanes, float>(j.mat, j.packed, j.n, j.nt, j.n_tiles,
-                                               j.tiles_per_chunk,
-                                               j.lab, j.P_pad, j.w, j.k, j.partial, u.chunk,
-                                               u.pgroup, sD, sWt);
+    if (j.packed)
+        plain_unit<kServeTile, kServeLanes, float, true>(j.mat, j.n, j.nt, j.n_tiles,
+                                                         j.tiles_per_chunk, j.lab, j.P_pad, j.w,
+                                                         j.k, j.partial, u.chunk, u.pgroup, sD,
+                                                         sWt);
+    else
+        plain_unit<kServeTile, kServeLanes, float, false>(j.mat, j.n, j.nt, j.n_tiles,
+                                                          j.tiles_per_chunk, j.lab, j.P_pad, j.w,
+                                                          j.k, j.partial, u.chunk, u.pgroup, sD,
+                                                          sWt);
 }
 
 template <int T, int LANES, typename Acc>
@@ -202,9 +216,14 @@ void launch_one(const PlainPlan &pl, const float *mat, int packed, int64_t n,
                 const uint16_t *lab, const double *w, int32_t k, double *partial, hipStream_t s) {
     const int64_t grid_real = pl.chunks * pl.pgroups;
     const int64_t gpad = round_up(grid_real, 8);  // xcd_logical needs a multiple of 8
-    hipLaunchKernelGGL((k_plain<T, LANES, Acc>), dim3((unsigned)gpad), dim3(LANES), 0, s, mat,
-                       packed, n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups, grid_real,
-                       lab, pl.P_pad, w, k, partial);
+    if (packed)
+        hipLaunchKernelGGL((k_plain<T, LANES, Acc, true>), dim3((unsigned)gpad), dim3(LANES), 0,
+                           s, mat, n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups,
+                           grid_real, lab, pl.P_pad, w, k, partial);
+    else
+        hipLaunchKernelGGL((k_plain<T, LANES, Acc, false>), dim3((unsigned)gpad), dim3(LANES), 0,
+                           s, mat, n, pl.n_t, pl.n_tiles, pl.tiles_per_chunk, pl.pgroups,
+                           grid_real, lab, pl.P_pad, w, k, partial);
 }
 
 // ---- few groupings at FP64 (the tie recheck) ---------------------------------
