@@ -161,33 +161,12 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
 #pragma unroll
         for (int ps = 0; ps < 8; ps++) {
             const int64_t i = r0 + ps * 16 + rq, j0 = c0 + cq;
-            if (vec == 1 && i < n && j0 + 3 < n) {
+            if (vec && i < n && j0 + 3 < n) {
                 const float4 v = *reinterpret_cast<const float4 *>(mat + (uint64_t)i * (uint64_t)n + j0);
                 d[ps][0] = v.x;
                 d[ps][1] = v.y;
                 d[ps][2] = v.z;
                 d[ps][3] = v.w;
-            } else if (vec == 2 && i < n && j0 > i && j0 + 3 < n) {
-                // packed rows start at any element: 16-, 8- or 4-byte reads
-                // by the row's alignment (all four entries lie in row i)
-                const int64_t x = d_index(i, j0, n, 1);
-                if ((x & 3) == 0) {
-                    const float4 v = *reinterpret_cast<const float4 *>(mat + x);
-                    d[ps][0] = v.x;
-                    d[ps][1] = v.y;
-                    d[ps][2] = v.z;
-                    d[ps][3] = v.w;
-                } else if ((x & 1) == 0) {
-                    const float2 a = *reinterpret_cast<const float2 *>(mat + x);
-                    const float2 b = *reinterpret_cast<const float2 *>(mat + x + 2);
-                    d[ps][0] = a.x;
-                    d[ps][1] = a.y;
-                    d[ps][2] = b.x;
-                    d[ps][3] = b.y;
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; e++) d[ps][e] = mat[x + e];
-                }
             } else {
                 // (the packed layout has no entries at j <= i)
 #pragma unroll
@@ -782,11 +761,10 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     const int64_t comp_units = panels * (panels + 1);
     // one s_T partial per work-group: no more work-groups than partial slots
     const int64_t blocks = prepass_blocks(n);
-    // 16-byte row reads: 1 = every row of the square is 16-byte aligned,
-    // 2 = packed with a 16-byte aligned start (each row's own alignment is
-    // checked in the kernel)
-    const bool al = (uintptr_t)mat % 16 == 0;
-    const int vec = packed ? (al ? 2 : 0) : ((n % 4 == 0) && al ? 1 : 0);
+    // 16-byte row reads where every row of the square is 16-byte aligned;
+    // packed rows start at any element and are read element by element
+    // (measured faster than 16/8/4-byte reads chosen by each row's alignment)
+    const int vec = !packed && (n % 4 == 0) && ((uintptr_t)mat % 16 == 0);
     const dim3 grid((unsigned)blocks);
     uint4 *t = (uint4 *)tiles;
     const PrepassRecheck none{};
