@@ -442,19 +442,29 @@ void sw_few_t(const float *mat, int64_t n, const LT *g, int64_t gstride, const i
     for (int64_t b = 0; b < m; b += kFewMaxM) {
         const int64_t mm = m - b < kFewMaxM ? m - b : kFewMaxM;
         const int64_t m_pad = round_up(mm, 8);
-        if (mm <= 4)
+        // whole groups of 16 groupings in one launch (one work-group row
+        // each), the rest with the narrowest instance that holds it
+        const int64_t full = mm > 16 ? mm / 16 : 0, rest = mm - 16 * full;
+        if (full > 0)
+            hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, (unsigned)full), dim3(256),
+                               0, s, mat, n, nt, tiles, tpc, g, gstride, rows + b, 16 * full, k, w,
+                               partial, m_pad, packed);
+        const int32_t *rr = rows + b + 16 * full;
+        double *pr = partial + 16 * full;
+        if (rest == 0) {
+        } else if (rest <= 4) {
             hipLaunchKernelGGL((k_sw_few<4, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
-                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
-        else if (mm <= 8)
+                               nt, tiles, tpc, g, gstride, rr, rest, k, w, pr, m_pad, packed);
+        } else if (rest <= 8) {
             hipLaunchKernelGGL((k_sw_few<8, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat, n,
-                               nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
-        else if (mm <= 12)
+                               nt, tiles, tpc, g, gstride, rr, rest, k, w, pr, m_pad, packed);
+        } else if (rest <= 12) {
             hipLaunchKernelGGL((k_sw_few<12, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat,
-                               n, nt, tiles, tpc, g, gstride, rows + b, mm, k, w, partial, m_pad, packed);
-        else
-            hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, (unsigned)ceil_div(mm, 16)),
-                               dim3(256), 0, s, mat, n, nt, tiles, tpc, g, gstride, rows + b, mm, k,
-                               w, partial, m_pad, packed);
+                               n, nt, tiles, tpc, g, gstride, rr, rest, k, w, pr, m_pad, packed);
+        } else {
+            hipLaunchKernelGGL((k_sw_few<16, LT>), dim3((unsigned)used, 1), dim3(256), 0, s, mat,
+                               n, nt, tiles, tpc, g, gstride, rr, rest, k, w, pr, m_pad, packed);
+        }
         hipLaunchKernelGGL(k_reduce_few, dim3((unsigned)mm), dim3(256), 0, s, partial, used, m_pad,
                            out + b);
     }
