@@ -23,8 +23,9 @@
 // weighted by w_g in FP64 afterwards, so FP32 only ever accumulates one K
 // chunk.
 //
-// Complement form (the whole test, where every grouping has the same group
-// sizes).  One group L (the largest) gets no columns: with e_L = 1 - sum of
+// Complement form (the whole test and serving jobs, where every grouping is a
+// permutation of the observed one and so has its group sizes).  One group L
+// (the largest) gets no columns: with e_L = 1 - sum of
 // the other one-hot columns,
 //     e_L^T U e_L = S - sum_{i: g(i) != L} v_i + sum_{g != L} N_g,
 // where S is the sum of U, v_i its row plus column sums, and
@@ -663,9 +664,9 @@ __global__ __launch_bounds__(256) void k_mfma(
                           lab, n_pad, cx != 0, kcol, Lg, P, z);
 }
 
-// Label-copy rounds for the permutations that COLS columns of k groups can
-// touch ((COLS - 1) / k + 2, 9 slots each, 256 per round), rounded up to the
-// instantiated counts.
+// Label-copy rounds for the permutations that COLS columns of k columns per
+// grouping can touch ((COLS - 1) / k + 2, 9 slots each, 256 per round),
+// rounded up to the instantiated counts.
 constexpr int kLqBins[5] = {2, 4, 5, 7, 10};
 // Static LDS of k_mfma<DT, NF, LQ>: two buffers of A (one 16 KB block per
 // component) and two of labels; gfx950 gives a work-group 160 KB.
