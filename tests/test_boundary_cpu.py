@@ -72,3 +72,18 @@ def test_packed_n():
     for bad in (0, 2, 4, 5, 4949):
         with pytest.raises(ps.PstatError):
             ps.packed_n(bad)
+
+
+def test_host_only_settings(lib):
+    # thread settings that need no device: layouts, path names and their
+    # resolution (PSTAT_EINVAL = -1 for unknown values)
+    assert lib.pstat_set_matrix_layout(0) == 0
+    assert lib.pstat_set_matrix_layout(1) == 0
+    assert lib.pstat_set_matrix_layout(2) == -1
+    assert lib.pstat_set_matrix_layout(0) == 0
+    lib.pstat_resolve_path.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int32]
+    assert lib.pstat_resolve_path(5, 1000, 3) == 5          # three-part split BF16
+    assert lib.pstat_resolve_path(-1, 10000, 5) == 3        # auto: split BF16
+    assert lib.pstat_resolve_path(-1, 10000, 40) == 0       # auto: plain FP32 above 16 groups
+    assert lib.pstat_resolve_path(6, 1000, 3) == -1
+    assert lib.pstat_free_workspace() == 0                  # none held

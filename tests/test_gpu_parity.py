@@ -639,3 +639,13 @@ def test_device_packed_generator_matches_square(ps):
         a = sd.uniform_packed(n, 77).cpu().numpy()
         b = packed(sd.uniform_matrix(n, 77)).cpu().numpy()
         assert np.array_equal(a, b)
+
+
+def test_free_workspace_between_calls(ps):
+    # the library-managed workspace is returned and allocated again
+    D, base, perms, w = problem(400, [100, 300], 64, mseed=41, pseed=42)
+    a = run_sW(ps, "mfma_split_bf16", D, perms, w)
+    ps.pstat_free_workspace()
+    ps.pstat_free_workspace()
+    b = run_sW(ps, "mfma_split_bf16", D, perms, w)
+    assert np.array_equal(a, b)
