@@ -249,7 +249,7 @@ __global__ __launch_bounds__(1024) void k_pvalue(const double *__restrict__ obs,
     red[threadIdx.x] = c;
     __syncthreads();
     for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) *p = P > 0 ? (double)(1 + red[0]) / (double)(1 + P) : NAN;
