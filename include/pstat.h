@@ -25,7 +25,8 @@
  * pstat_workspace_bytes); otherwise the library allocates and caches its own.
  *
  * Layouts.  mat is n x n float32, row-major, 64-bit element offsets
- * (row * n + col); only the strict upper triangle (col > row) is ever read.
+ * (row * n + col); only the strict upper triangle (col > row) is ever read,
+ * so it may also be given alone, packed (pstat_set_matrix_layout).
  * groupings is int32, permutation-major: row p (n labels) starts at p * n.
  * Labels are group indices 0 <= g < k (k <= 65535) and index inv_group_sizes.
  */
@@ -179,7 +180,11 @@ int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed
  * groups among the n_groups labels.  result (device, 4 doubles) =
  * {F_obs, p, s_W_obs, s_T}; sW_all (device, n_perms + 1 doubles, may be NULL)
  * receives s_W of the observed grouping then of each shuffle; n_rechecked
- * (host, may be NULL) receives how many permutations were recomputed. */
+ * (host, may be NULL) receives how many permutations were recomputed.  On
+ * the MFMA forms every grouping here has the observed group sizes, so the
+ * largest group's within-group sum is taken as the complement of the others
+ * (k - 1 one-hot columns instead of k); its values agree with pstat_sW's to
+ * the form's tolerance, not bit for bit. */
 int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_t n_groups,
                     int64_t n_perms, uint64_t seed, double *result, double *sW_all,
                     int64_t *n_rechecked);
