@@ -154,9 +154,20 @@ int pstat_sT(const float *mat, int64_t n, double *s_T);
 int pstat_F(const double *s_W, int64_t count, const double *s_T, int64_t n, int32_t k,
             double *F);
 
-/* *p = (1 + #{q : s_W_perm[q] <= *s_W_obs}) / (1 + n_perms), FP64, device
- * scalars; equal to the count of F_q >= F_obs for k >= 2, n > k, s_W > 0.
- * n_perms = 0 gives NaN. */
+/* Relative tie tolerance of the p-value (a reading of the permutation test of
+ * section 1): a permutation's statistic counts as at least as extreme as the
+ * observed one when s_W_perm <= s_W_obs + PSTAT_TIE_RTOL * |s_W_obs|.
+ * Groupings whose s_W are equal in exact arithmetic -- the observed partition
+ * reached again under other labels, any grouping of a constant matrix -- then
+ * tie whatever order their FP64 sums were taken in (FP64 rounding of s_W is
+ * ~1e-13 relative at n = 10^5), while statistics that differ by more than
+ * 1e-10 are told apart (FP32 storage of d already blurs s_W at ~1e-8). */
+#define PSTAT_TIE_RTOL 1e-10
+
+/* *p = (1 + #{q : s_W_perm[q] <= *s_W_obs + PSTAT_TIE_RTOL |*s_W_obs|}) /
+ * (1 + n_perms), FP64, device scalars: the count of F_q >= F_obs (F falls as
+ * s_W grows, for k >= 2, n > k, s_W > 0) with ties taken at that tolerance.
+ * NaN values never count.  n_perms = 0 gives NaN. */
 int pstat_pvalue(const double *s_W_obs, const double *s_W_perm, int64_t n_perms, double *p);
 
 /* inv[g] = 1 / #{i : grouping[i] == g} for g < n_groups (0 for an empty group),
@@ -173,9 +184,14 @@ int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed
 /* The whole permutation test on one matrix, all on the device:
  * weights 1/n_g from `grouping` (n_groups groups), n_perms shuffles
  * (pstat_permute with `seed`), s_W of the observed grouping and of every
- * shuffle, s_T, F and p.  The observed grouping, the first 15 shuffles and
- * every shuffle whose s_W lies within the path's error band of the observed
- * value are recomputed in FP64 before counting; the call SYNCHRONISES the
+ * shuffle, s_T, F and p (as pstat_pvalue, ties at PSTAT_TIE_RTOL).  The
+ * observed grouping and the first 15 shuffles are recomputed in FP64; the
+ * largest relative error of the form over those 16, times 16, is the band
+ * (at least 1e-13): every shuffle whose s_W lies within the band of the
+ * p-value's edge (from the observed value to PSTAT_TIE_RTOL above it) is
+ * recomputed in FP64 too before counting.  The band is measured, not a
+ * proven bound: a shuffle outside it whose error exceeded it could land on
+ * the wrong side.  The call SYNCHRONISES the
  * stream twice (label check, count of near ties).  F counts the non-empty
  * groups among the n_groups labels.  result (device, 4 doubles) =
  * {F_obs, p, s_W_obs, s_T}; sW_all (device, n_perms + 1 doubles, may be NULL)

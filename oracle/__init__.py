@@ -34,6 +34,15 @@ def build(force: bool = False) -> str:
 
 _lib = None
 
+# Relative tie tolerance of the p-value count (a reading of the permutation
+# test of section 1): permutation q counts as at least as extreme as the
+# observed grouping when s_W[q] <= s_W_obs + TIE_RTOL * |s_W_obs|.  Groupings
+# whose statistics are equal in exact arithmetic (the same partition under
+# other labels, or any grouping of a constant matrix) then tie whatever the
+# FP64 summation order; 1e-10 sits far above FP64 rounding of s_W (~1e-13 at
+# n = 10^5) and far below the spread of s_W across permutations.
+TIE_RTOL = 1e-10
+
 
 def lib() -> ctypes.CDLL:
     global _lib
@@ -43,19 +52,21 @@ def lib() -> ctypes.CDLL:
         P = ctypes.c_void_p
         i64, i32, u64, f64, c_int = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.c_double, ctypes.c_int)
-        L.oracle_sW_rows.argtypes = [P, i64, i64, i64, P, i64, P, P, c_int]
-        L.oracle_sW.argtypes = [P, i64, P, i64, P, P, c_int]
-        L.oracle_sW_tiled.argtypes = [P, i64, P, i64, P, i64, P, c_int]
-        L.oracle_sq_rows.argtypes = [P, i64, i64, i64, P]
+        L.oracle_group_sums.argtypes = [P, i64, i64, i64, P, i64, i32, P, c_int]
+        L.oracle_group_sums.restype = c_int
+        L.oracle_sW_from_sums.argtypes = [P, i64, i32, P, P]
+        L.oracle_sW.argtypes = [P, i64, P, i64, i32, P, P, c_int]
+        L.oracle_sW.restype = c_int
+        L.oracle_sq_sum.argtypes = [P, i64, i64, i64, P]
         L.oracle_sT.argtypes = [P, i64]
         L.oracle_sT.restype = f64
         L.oracle_between_unweighted.argtypes = [P, i64, P]
         L.oracle_between_unweighted.restype = f64
         L.oracle_F.argtypes = [P, i64, f64, i64, i32, P]
-        L.oracle_pvalue.argtypes = [f64, P, i64]
+        L.oracle_pvalue_F.argtypes = [f64, P, i64]
+        L.oracle_pvalue_F.restype = f64
+        L.oracle_pvalue.argtypes = [f64, P, i64, f64]
         L.oracle_pvalue.restype = f64
-        L.oracle_pvalue_sW.argtypes = [f64, P, i64]
-        L.oracle_pvalue_sW.restype = f64
         L.oracle_splitmix64_next.argtypes = [P]
         L.oracle_splitmix64_next.restype = u64
         L.oracle_stream_start.argtypes = [u64, u64]
@@ -85,54 +96,80 @@ def _groupings(groupings, n: int) -> np.ndarray:
     g = np.ascontiguousarray(groupings, dtype=np.int32)
     if g.ndim == 1:
         g = g[None, :]
-    if g.shape[1] != n:
+    if g.ndim != 2 or g.shape[1] != n:
         raise ValueError("groupings must have n columns")
     return g
+
+
+def _k_of(g: np.ndarray, k: int | None) -> int:
+    if k is None:
+        k = int(g.max()) + 1 if g.size else 1
+    if g.size and (int(g.min()) < 0 or int(g.max()) >= k):
+        raise ValueError(f"labels must lie in [0, {k})")
+    return int(k)
+
+
+def _weights(inv, k: int) -> np.ndarray:
+    w = np.ascontiguousarray(inv, dtype=np.float64).reshape(-1)
+    if w.shape[0] < k:
+        raise ValueError(f"need {k} weights, got {w.shape[0]}")
+    return w
 
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
 
 
-def sW(mat, groupings, inv, nthreads: int = 0) -> np.ndarray:
-    """s_W for every grouping row (Algorithm 1, FP64)."""
+def sW(mat, groupings, inv, nthreads: int = 0, k: int | None = None) -> np.ndarray:
+    """s_W of every grouping row: the weighted within-group sums of squared
+    distances (the quantity of section 2, Algorithm 1), FP64."""
     mat = _mat(mat)
     n = mat.shape[0]
     g = _groupings(groupings, n)
-    inv = np.ascontiguousarray(inv, dtype=np.float64)
+    k = _k_of(g, k)
+    w = _weights(inv, k)
     out = np.zeros(g.shape[0], dtype=np.float64)
-    lib().oracle_sW(_ptr(mat), n, _ptr(g), g.shape[0], _ptr(inv), _ptr(out), nthreads)
+    if lib().oracle_sW(_ptr(mat), n, _ptr(g), g.shape[0], k, _ptr(w), _ptr(out), nthreads):
+        raise RuntimeError("oracle_sW failed")
     return out
 
 
-def sW_rows(rows, row0: int, n: int, groupings, inv, acc: np.ndarray, nthreads: int = 0) -> None:
-    """Continue acc[p] over matrix rows [row0, row0 + rows.shape[0])."""
+def new_group_sums(n_groupings: int, k: int) -> np.ndarray:
+    """Zeroed compensated accumulators for group_sums: [groupings, k, 2]."""
+    return np.zeros((n_groupings, k, 2), dtype=np.float64)
+
+
+def group_sums(rows, row0: int, n: int, groupings, sums: np.ndarray, nthreads: int = 0) -> None:
+    """Continue the within-group sums over matrix rows [row0, row0 + rows.shape[0])
+    (so a matrix too large for the host can be fed in row blocks, in order)."""
     rows = np.ascontiguousarray(rows, dtype=np.float32)
     assert rows.ndim == 2 and rows.shape[1] == n
     g = _groupings(groupings, n)
-    inv = np.ascontiguousarray(inv, dtype=np.float64)
-    assert acc.dtype == np.float64 and acc.flags.c_contiguous and acc.shape[0] == g.shape[0]
-    lib().oracle_sW_rows(_ptr(rows), row0, rows.shape[0], n, _ptr(g), g.shape[0], _ptr(inv),
-                         _ptr(acc), nthreads)
+    k = sums.shape[1]
+    _k_of(g, k)
+    assert sums.dtype == np.float64 and sums.flags.c_contiguous
+    assert sums.shape == (g.shape[0], k, 2)
+    if lib().oracle_group_sums(_ptr(rows), row0, rows.shape[0], n, _ptr(g), g.shape[0], k,
+                               _ptr(sums), nthreads):
+        raise RuntimeError("oracle_group_sums failed")
 
 
-def sW_tiled(mat, groupings, inv, tile: int, nthreads: int = 0) -> np.ndarray:
-    """s_W in Algorithm 2's tiled traversal (FP64)."""
-    mat = _mat(mat)
-    n = mat.shape[0]
-    g = _groupings(groupings, n)
-    inv = np.ascontiguousarray(inv, dtype=np.float64)
-    out = np.zeros(g.shape[0], dtype=np.float64)
-    lib().oracle_sW_tiled(_ptr(mat), n, _ptr(g), g.shape[0], _ptr(inv), int(tile), _ptr(out),
-                          nthreads)
+def sW_from_sums(sums: np.ndarray, inv) -> np.ndarray:
+    """s_W = sum_c w_c S_c from group_sums' accumulators."""
+    k = sums.shape[1]
+    w = _weights(inv, k)
+    out = np.zeros(sums.shape[0], dtype=np.float64)
+    lib().oracle_sW_from_sums(_ptr(np.ascontiguousarray(sums)), sums.shape[0], k, _ptr(w),
+                              _ptr(out))
     return out
 
 
-def sq_rows(rows, row0: int, n: int, acc: float) -> float:
+def sq_sum(rows, row0: int, n: int, acc: np.ndarray) -> None:
+    """Continue the compensated sum acc (2 doubles) of d^2 above the diagonal
+    over matrix rows [row0, row0 + rows.shape[0]); s_T = acc.sum() / n."""
     rows = np.ascontiguousarray(rows, dtype=np.float32)
-    a = np.array([acc], dtype=np.float64)
-    lib().oracle_sq_rows(_ptr(rows), row0, rows.shape[0], n, _ptr(a))
-    return float(a[0])
+    assert acc.dtype == np.float64 and acc.shape == (2,)
+    lib().oracle_sq_sum(_ptr(rows), row0, rows.shape[0], n, _ptr(acc))
 
 
 def sT(mat) -> float:
@@ -142,8 +179,7 @@ def sT(mat) -> float:
 
 def between_unweighted(mat, grouping) -> float:
     mat = _mat(mat)
-    g = _groupings(grouping, mat.shape[0])[0]
-    g = np.ascontiguousarray(g)
+    g = np.ascontiguousarray(_groupings(grouping, mat.shape[0])[0])
     return float(lib().oracle_between_unweighted(_ptr(mat), mat.shape[0], _ptr(g)))
 
 
@@ -154,14 +190,16 @@ def F(sW_values, sT_value: float, n: int, k: int) -> np.ndarray:
     return out
 
 
-def pvalue(F_obs: float, F_perm) -> float:
+def pvalue_F(F_obs: float, F_perm) -> float:
+    """Textbook count: (1 + #{F_q >= F_obs}) / (1 + P)."""
     f = np.ascontiguousarray(F_perm, dtype=np.float64)
-    return float(lib().oracle_pvalue(float(F_obs), _ptr(f), f.shape[0]))
+    return float(lib().oracle_pvalue_F(float(F_obs), _ptr(f), f.shape[0]))
 
 
-def pvalue_sW(sW_obs: float, sW_perm) -> float:
+def pvalue(sW_obs: float, sW_perm, rtol: float = TIE_RTOL) -> float:
+    """(1 + #{s_W[q] <= s_W_obs + rtol |s_W_obs|}) / (1 + P)."""
     s = np.ascontiguousarray(sW_perm, dtype=np.float64)
-    return float(lib().oracle_pvalue_sW(float(sW_obs), _ptr(s), s.shape[0]))
+    return float(lib().oracle_pvalue(float(sW_obs), _ptr(s), s.shape[0], float(rtol)))
 
 
 def splitmix64_stream(state: int, count: int) -> list[int]:
@@ -170,7 +208,8 @@ def splitmix64_stream(state: int, count: int) -> list[int]:
 
 
 def stream_start(seed: int, p: int) -> int:
-    return int(lib().oracle_stream_start(seed, p))
+    m = (1 << 64) - 1
+    return int(lib().oracle_stream_start(int(seed) & m, int(p) & m))
 
 
 def bounded(state: int, s: int, count: int) -> list[int]:
@@ -182,7 +221,8 @@ def permute(base, n_perms: int, seed: int, nthreads: int = 0) -> np.ndarray:
     """n_perms Fisher-Yates shuffles of base, int32 [n_perms, n]."""
     base = np.ascontiguousarray(base, dtype=np.int32)
     out = np.empty((n_perms, base.shape[0]), dtype=np.int32)
-    lib().oracle_permute(_ptr(base), base.shape[0], n_perms, seed, _ptr(out), nthreads)
+    lib().oracle_permute(_ptr(base), base.shape[0], n_perms, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                         _ptr(out), nthreads)
     return out
 
 
@@ -197,9 +237,11 @@ def group_sizes(grouping, k: int | None = None) -> np.ndarray:
     return np.bincount(g, minlength=k or 0)
 
 
-def permanova(mat, grouping, n_perms: int, seed: int, nthreads: int = 0) -> dict:
+def permanova(mat, grouping, n_perms: int, seed: int, nthreads: int = 0,
+              rtol: float = TIE_RTOL) -> dict:
     """The whole test: weights 1/n_g from the observed grouping, n_perms
-    shuffles, s_W for the observed grouping and every shuffle, s_T, F, p."""
+    shuffles, s_W for the observed grouping and every shuffle, s_T, F, and p
+    (tie tolerance rtol; p_F is the textbook count on F, without it)."""
     mat = _mat(mat)
     n = mat.shape[0]
     grouping = np.ascontiguousarray(grouping, dtype=np.int32)
@@ -208,8 +250,9 @@ def permanova(mat, grouping, n_perms: int, seed: int, nthreads: int = 0) -> dict
     inv = np.where(sizes > 0, 1.0 / np.maximum(sizes, 1), 0.0).astype(np.float64)
     perms = permute(grouping, n_perms, seed, nthreads)
     allg = np.vstack([grouping[None, :], perms])
-    s = sW(mat, allg, inv, nthreads)
+    s = sW(mat, allg, inv, nthreads, k=len(sizes))
     t = sT(mat)
     f = F(s, t, n, k)
     return dict(sW_obs=float(s[0]), sW_perm=s[1:], sT=t, F_obs=float(f[0]), F_perm=f[1:],
-                p=pvalue(float(f[0]), f[1:]), k=k, inv=inv, perms=perms)
+                p=pvalue(float(s[0]), s[1:], rtol), p_F=pvalue_F(float(f[0]), f[1:]), k=k,
+                inv=inv, perms=perms)

@@ -138,6 +138,37 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> int:
     return t.data_ptr()
 
 
+def _need(t, count: int, name: str) -> None:
+    """Size check before any launch: t must be a tensor of at least `count`
+    elements (the library reads or writes that many through its pointer)."""
+    if not isinstance(t, torch.Tensor):
+        raise PstatError(PSTAT_EINVAL, f"{name} must be a tensor")
+    if t.numel() < count:
+        raise PstatError(PSTAT_EINVAL, f"{name} holds {t.numel()} elements, {count} needed")
+
+
+def _rows(groupings: torch.Tensor, n: int, name: str = "groupings") -> int:
+    """Number of grouping rows of a [P, n] (or one [n]) label tensor."""
+    if not isinstance(groupings, torch.Tensor):
+        raise PstatError(PSTAT_EINVAL, f"{name} must be a tensor")
+    if groupings.dim() == 1 and groupings.shape[0] == n:
+        return 1
+    if groupings.dim() == 2 and groupings.shape[1] == n:
+        return int(groupings.shape[0])
+    raise PstatError(PSTAT_EINVAL, f"{name} must be [P, {n}] or [{n}], got {tuple(groupings.shape)}")
+
+
+def _mat_n(mat: torch.Tensor) -> int:
+    """n of a matrix argument (square n x n, or packed strict upper triangle)."""
+    if not isinstance(mat, torch.Tensor):
+        raise PstatError(PSTAT_EINVAL, "mat must be a tensor")
+    if mat.dim() == 2 and mat.shape[0] == mat.shape[1]:
+        return int(mat.shape[0])
+    if mat.dim() == 1:
+        return packed_n(mat.numel())
+    raise PstatError(PSTAT_EINVAL, f"mat must be n x n or packed 1-D, got {tuple(mat.shape)}")
+
+
 def packed_n(length: int) -> int:
     """n of a strict upper triangle packed into `length` = n (n - 1) / 2 floats."""
     n = (1 + math.isqrt(1 + 8 * int(length))) // 2
@@ -150,13 +181,9 @@ def _mat(mat: torch.Tensor) -> tuple[int, int]:
     """Pointer and n of a matrix argument, setting this thread's layout: an
     n x n tensor is the square layout, a 1-D tensor of n (n - 1) / 2 floats
     the packed strict upper triangle."""
+    n = _mat_n(mat)
     ptr = _dev(mat, torch.float32, "mat")
-    if mat.dim() == 2 and mat.shape[0] == mat.shape[1]:
-        layout, n = PSTAT_LAYOUT_SQUARE, mat.shape[0]
-    elif mat.dim() == 1:
-        layout, n = PSTAT_LAYOUT_UPPER_PACKED, packed_n(mat.numel())
-    else:
-        raise PstatError(PSTAT_EINVAL, f"mat must be n x n or packed 1-D, got {tuple(mat.shape)}")
+    layout = PSTAT_LAYOUT_UPPER_PACKED if mat.dim() == 1 else PSTAT_LAYOUT_SQUARE
     _check(_lib.pstat_set_matrix_layout(layout))
     return ptr, n
 
@@ -210,8 +237,16 @@ def pstat_workspace_bytes(n: int, n_perms: int, n_groups: int, path=PSTAT_PATH_A
 
 def pstat_sW(mat: torch.Tensor, groupings: torch.Tensor, inv_group_sizes: torch.Tensor,
              out: torch.Tensor | None = None) -> torch.Tensor:
-    """s_W of every grouping row (validates labels; synchronises once)."""
-    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    """s_W of every grouping row (validates labels; synchronises once).  The
+    library takes k = 1 + the largest label and reads that many weights."""
+    P = _rows(groupings, _mat_n(mat))
+    if out is not None:
+        _need(out, P, "out")
+    _need(inv_group_sizes, 1, "inv_group_sizes")
+    if groupings.numel() and isinstance(groupings, torch.Tensor) and groupings.is_cuda:
+        # argument check: the weights must cover the largest label (one
+        # reduction; the call synchronises anyway)
+        _need(inv_group_sizes, int(groupings.max().item()) + 1, "inv_group_sizes")
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
@@ -225,7 +260,10 @@ def pstat_sW(mat: torch.Tensor, groupings: torch.Tensor, inv_group_sizes: torch.
 
 def pstat_sW_k(mat, groupings, n_groups: int, inv_group_sizes, out=None) -> torch.Tensor:
     """s_W with the number of groups given; asynchronous."""
-    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    P = _rows(groupings, _mat_n(mat))
+    _need(inv_group_sizes, int(n_groups), "inv_group_sizes")
+    if out is not None:
+        _need(out, P, "out")
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
@@ -243,6 +281,9 @@ def pstat_check_labels() -> None:
 
 
 def pstat_sT(mat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    _mat_n(mat)
+    if out is not None:
+        _need(out, 1, "s_T")
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
@@ -254,6 +295,10 @@ def pstat_sT(mat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor
 
 def pstat_F(s_W: torch.Tensor, s_T: torch.Tensor, n: int, k: int,
             out: torch.Tensor | None = None) -> torch.Tensor:
+    _need(s_W, 0, "s_W")
+    _need(s_T, 1, "s_T")
+    if out is not None:
+        _need(out, s_W.numel(), "F")
     if out is None:
         out = torch.empty_like(s_W)
     _ready(s_W.device)
@@ -265,6 +310,10 @@ def pstat_F(s_W: torch.Tensor, s_T: torch.Tensor, n: int, k: int,
 
 def pstat_pvalue(s_W_obs: torch.Tensor, s_W_perm: torch.Tensor,
                  out: torch.Tensor | None = None) -> torch.Tensor:
+    _need(s_W_obs, 1, "s_W_obs")
+    _need(s_W_perm, 0, "s_W_perm")
+    if out is not None:
+        _need(out, 1, "p")
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=s_W_obs.device)
     _ready(s_W_obs.device)
@@ -276,6 +325,9 @@ def pstat_pvalue(s_W_obs: torch.Tensor, s_W_perm: torch.Tensor,
 
 def pstat_group_weights(grouping: torch.Tensor, n_groups: int,
                         out: torch.Tensor | None = None) -> torch.Tensor:
+    _need(grouping, 1, "grouping")
+    if out is not None:
+        _need(out, int(n_groups), "inv")
     if out is None:
         out = torch.empty(n_groups, dtype=torch.float64, device=grouping.device)
     _ready(grouping.device)
@@ -286,7 +338,10 @@ def pstat_group_weights(grouping: torch.Tensor, n_groups: int,
 
 def pstat_permute(base: torch.Tensor, n_perms: int, seed: int,
                   out: torch.Tensor | None = None) -> torch.Tensor:
+    _need(base, 1, "base")
     n = base.numel()
+    if out is not None:
+        _need(out, int(n_perms) * n, "groupings")
     if out is None:
         out = torch.empty((n_perms, n), dtype=torch.int32, device=base.device)
     _ready(base.device)
@@ -299,6 +354,14 @@ def pstat_permanova(mat: torch.Tensor, grouping: torch.Tensor, n_groups: int, n_
                     seed: int, result: torch.Tensor | None = None,
                     sW_all: torch.Tensor | None = None) -> tuple[torch.Tensor, int]:
     """The whole test.  Returns (result = [F_obs, p, s_W_obs, s_T], n_rechecked)."""
+    n = _mat_n(mat)
+    _need(grouping, n, "grouping")
+    if grouping.numel() != n:
+        raise PstatError(PSTAT_EINVAL, f"grouping must hold n = {n} labels")
+    if result is not None:
+        _need(result, 4, "result")
+    if sW_all is not None:
+        _need(sW_all, int(n_perms) + 1, "sW_all")
     if result is None:
         result = torch.empty(4, dtype=torch.float64, device=mat.device)
     _ready(mat.device)
@@ -313,6 +376,12 @@ def pstat_permanova(mat: torch.Tensor, grouping: torch.Tensor, n_groups: int, n_
     return result, int(rechecked.value)
 
 
+# n of each registered matrix (argument checks of pstat_sW_registered)
+_registered_n: dict[int, int] = {}
+# grouping rows (n_perms + 1) of each live serving job, by (server, job)
+_job_rows: dict[tuple[int, int], int] = {}
+
+
 def pstat_matrix_register(mat: torch.Tensor, path=PSTAT_PATH_AUTO) -> int:
     p = PATH_IDS[path] if isinstance(path, str) else int(path)
     _ready(mat.device)
@@ -320,16 +389,24 @@ def pstat_matrix_register(mat: torch.Tensor, path=PSTAT_PATH_AUTO) -> int:
     mp, n = _mat(mat)
     _check(_lib.pstat_matrix_register(mp, n, p,
                                       ctypes.byref(h)))
+    _registered_n[int(h.value)] = n
     return int(h.value)
 
 
 def pstat_matrix_release(handle: int) -> None:
     _check(_lib.pstat_matrix_release(int(handle)))
+    _registered_n.pop(int(handle), None)
 
 
 def pstat_sW_registered(handle: int, groupings: torch.Tensor, n_groups: int,
                         inv_group_sizes: torch.Tensor, out: torch.Tensor | None = None):
-    P = groupings.shape[0] if groupings.dim() == 2 else 1
+    n = _registered_n.get(int(handle))
+    if n is None:
+        raise PstatError(PSTAT_EINVAL, f"unknown handle {handle}")
+    P = _rows(groupings, n)
+    _need(inv_group_sizes, int(n_groups), "inv_group_sizes")
+    if out is not None:
+        _need(out, P, "out")
     if out is None:
         out = torch.empty(P, dtype=torch.float64, device=groupings.device)
     _ready(groupings.device)
@@ -362,6 +439,10 @@ def pstat_job_create(server: int, mat: torch.Tensor, grouping: torch.Tensor, n_g
                      path=PSTAT_PATH_PLAIN_F32) -> tuple[int, int]:
     """Returns (job id, number of work units)."""
     p = PATH_IDS[path] if isinstance(path, str) else int(path)
+    n = _mat_n(mat)
+    _need(grouping, n, "grouping")
+    if grouping.numel() != n:
+        raise PstatError(PSTAT_EINVAL, f"grouping must hold n = {n} labels")
     _ready(mat.device)
     job, units = _i64(0), _i64(0)
     mp, n = _mat(mat)
@@ -370,6 +451,7 @@ def pstat_job_create(server: int, mat: torch.Tensor, grouping: torch.Tensor, n_g
                                  int(n_perms), int(seed) & 0xFFFFFFFFFFFFFFFF, p,
                                  _dev(scratch, torch.uint8, "scratch"), scratch.numel(),
                                  ctypes.byref(job), ctypes.byref(units)))
+    _job_rows[(int(server), int(job.value))] = int(n_perms) + 1
     return int(job.value), int(units.value)
 
 
@@ -383,6 +465,11 @@ def pstat_serve_round(server: int, pairs) -> None:
 
 def pstat_job_finish(server: int, job: int, sW_all: torch.Tensor | None = None):
     """Returns ([F_obs, p, s_W_obs, s_T], n_rechecked)."""
+    if sW_all is not None:
+        rows = _job_rows.get((int(server), int(job)))
+        if rows is None:
+            raise PstatError(PSTAT_EINVAL, f"unknown job {job}")
+        _need(sW_all, rows, "sW_all")
     _ready(torch.device("cuda", torch.cuda.current_device()))
     res = (ctypes.c_double * 4)()
     rech = _i64(0)
@@ -393,6 +480,7 @@ def pstat_job_finish(server: int, job: int, sW_all: torch.Tensor | None = None):
 
 def pstat_job_release(server: int, job: int) -> None:
     _check(_lib.pstat_job_release(int(server), int(job)))
+    _job_rows.pop((int(server), int(job)), None)
 
 
 def pstat_profile(on: bool) -> None:

@@ -230,8 +230,10 @@ void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int3
               double *F, hipStream_t s);
 void launch_pvalue(const double *sW_obs, const double *sW_perm, int64_t P, double *p,
                    hipStream_t s);
-// Rows q in [q0, R) of sW_all with |sW_all[q] - sW_all[0]| <= *band * |sW_all[0]|
-// go to list (row indices); *count (zeroed by the caller) = number flagged.
+// Rows q in [q0, R) of sW_all with sW_all[0] (1 - *band) <= sW_all[q] <=
+// sW_all[0] (1 + PSTAT_TIE_RTOL + *band) (sW_all[0] >= 0) go to list (row
+// indices): every row whose side of the p-value's edge could be wrong by
+// *band; *count (zeroed by the caller) = number flagged.
 void launch_flag_ties(const double *sW_all, int64_t q0, int64_t R, const double *band,
                       int32_t *list, int32_t *count, hipStream_t s);
 // *band = margin * max_j |fast[j] - exact[j]| / |exact[0]|, j < S, floor 1e-13.

@@ -2,6 +2,7 @@
 // F, the permutation p-value and the tie band of the p-value recheck.
 #include <math.h>
 
+#include "../../include/pstat.h"
 #include "internal.h"
 
 namespace pstat {
@@ -238,13 +239,14 @@ __global__ void k_F(const double *__restrict__ sW, int64_t count, const double *
         F[i] = pseudo_F(sW[i], t, n, k);
 }
 
-// One block: count s_W_perm[q] <= s_W_obs (NaN compares false).
+// One block: count s_W_perm[q] <= s_W_obs + PSTAT_TIE_RTOL |s_W_obs| (NaN
+// compares false).
 __global__ __launch_bounds__(1024) void k_pvalue(const double *__restrict__ obs,
                                                  const double *__restrict__ perm, int64_t P,
                                                  double *__restrict__ p) {
-    const double o = *obs;
+    const double edge = *obs + PSTAT_TIE_RTOL * fabs(*obs);
     unsigned long long c = 0;
-    for (int64_t q = threadIdx.x; q < P; q += 1024) c += (perm[q] <= o) ? 1ull : 0ull;
+    for (int64_t q = threadIdx.x; q < P; q += 1024) c += (perm[q] <= edge) ? 1ull : 0ull;
     __shared__ unsigned long long red[1024];
     red[threadIdx.x] = c;
     __syncthreads();
@@ -255,16 +257,20 @@ __global__ __launch_bounds__(1024) void k_pvalue(const double *__restrict__ obs,
     if (threadIdx.x == 0) *p = P > 0 ? (double)(1 + red[0]) / (double)(1 + P) : NAN;
 }
 
-// rows q in [q0, R) of sW_all with |sW_all[q] - sW_all[0]| <= *band * |sW_all[0]|
-// are appended to list.
+// rows q in [q0, R) of sW_all whose value lies within *band (relative to
+// |sW_all[0]|) of the p-value's decision interval [.., sW_all[0] (1 + tie
+// tolerance)] edges are appended to list: from sW_all[0] (1 - band) to
+// sW_all[0] (1 + tie tolerance + band).
 __global__ void k_flag_ties(const double *__restrict__ sW_all, int64_t q0, int64_t R,
                             const double *__restrict__ band, int32_t *__restrict__ list,
                             int32_t *__restrict__ count) {
     const double o = sW_all[0];
-    const double tol = *band * fabs(o);
+    const double lo = o - *band * fabs(o);
+    const double hi = o + (*band + PSTAT_TIE_RTOL) * fabs(o);
     for (int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < R;
          q += (int64_t)gridDim.x * blockDim.x) {
-        if (fabs(sW_all[q] - o) <= tol) {
+        const double v = sW_all[q];
+        if (v >= lo && v <= hi) {
             const int32_t at = atomicAdd(count, 1);
             list[at] = (int32_t)q;
         }

@@ -153,17 +153,18 @@ def test_n100000_sampled(ps):
     sample = [0, 1, 2, 3, 250, 500, 750, P - 1]           # permutation indices
     rows = np.vstack([base, perms[sample]])
     w = synth.inv_group_sizes(cfg["sizes"])
-    acc = np.zeros(rows.shape[0])
-    sq = 0.0
+    sums = oracle.new_group_sums(rows.shape[0], k)
+    sq = np.zeros(2)
     block = 1000
     host = torch.empty((block, n), dtype=torch.float32, pin_memory=True)
     for r0 in range(0, n, block):
         r1 = min(n, r0 + block)
         host[: r1 - r0].copy_(D[r0:r1])
         blk = host[: r1 - r0].numpy()
-        oracle.sW_rows(blk, r0, n, rows, w, acc)
-        sq = oracle.sq_rows(blk, r0, n, sq)
-    sT = sq / n
+        oracle.group_sums(blk, r0, n, rows, sums)
+        oracle.sq_sum(blk, r0, n, sq)
+    acc = oracle.sW_from_sums(sums, w)
+    sT = sq.sum() / n
     F_obs = oracle.F(acc[:1], sT, n, k)[0]
     out = {}
     g = torch.from_numpy(rows).cuda()
@@ -179,11 +180,10 @@ def test_n100000_sampled(ps):
         if path in ("plain_f32", "mfma_split_bf16"):
             assert max_rel(got, acc) <= 1e-5, (path, out[path])
         assert abs(res[0] - F_obs) <= 1e-5 * abs(F_obs)
-        # the oracle's s_T is one sequential FP64 sum of 5e9 terms: its own
-        # rounding is ~sqrt(5e9) * 2^-53 ~ 1e-11 relative
-        assert abs(res[3] - sT) <= 1e-10 * sT
+        assert abs(res[3] - sT) <= 1e-12 * sT
         # p is the count of the returned s_W at or below the observed one
-        assert res[1] == (1 + np.sum(sw[1:] <= sw[0])) / (1 + P)
+        # (ties within the tolerance included)
+        assert res[1] == oracle.pvalue(sw[0], sw[1:])
     record("n100000", dict(sample=sample, F_obs=F_obs, forms=out))
 
 

@@ -325,7 +325,7 @@ def test_sT_F_pvalue_kernels(ps):
     Fo = oracle.F(sW, sT, 500, 3)
     assert np.max(np.abs(Fd - Fo) / np.maximum(np.abs(Fo), 1.0)) <= 1e-13
     p = ps.pstat_pvalue(swd[:1], swd[1:]).item()
-    assert p == oracle.pvalue_sW(sW[0], sW[1:])
+    assert p == oracle.pvalue(sW[0], sW[1:])
     empty = torch.empty(0, dtype=torch.float64, device="cuda")
     assert np.isnan(ps.pstat_pvalue(swd[:1], empty).item())
 
@@ -538,6 +538,57 @@ def test_permanova_tiny_and_ragged(ps, path, n, sizes, P):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert res[1] == ref["p"]
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+
+
+# Ties are counted with a relative tolerance on both sides (the library's
+# PSTAT_TIE_RTOL, the oracle's TIE_RTOL).  (1) Two equal groups: a shuffle
+# that reproduces the observed partition under swapped labels has the
+# observed s_W in exact arithmetic, whichever kernel computed each value
+# (on the MFMA forms the observed value comes from the pre-pass, the flagged
+# rows from the recheck kernel); seed 12 at n = 12 reaches it.  (2) A
+# constant matrix: every grouping has the same s_W in exact arithmetic, so
+# p = 1, also when the weights 1/n_g are not exact.
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("n,half", [(12, 6), (20, 10)])
+def test_permanova_swapped_partition_ties(ps, path, n, half):
+    import torch
+    D = synth.uniform_matrix(n, 40 + n)
+    base = synth.base_labels([half, half])
+    P, seed = 999, 12
+    ref = oracle.permanova(D, base, P, seed)
+    same = sum(np.array_equal(p, base) or np.array_equal(p, 1 - base) for p in ref["perms"])
+    if n == 12:
+        assert same >= 1
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, 2, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    assert res[1] == ref["p"], (res[1], ref["p"], rechecked, same)
+    assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
+@pytest.mark.parametrize("sizes,c", [([60, 100, 140], 0.5), ([3, 5, 7, 11], 0.3),
+                                     ([8, 16, 32, 8], 0.5)])
+def test_permanova_constant_matrix_ties(ps, path, sizes, c):
+    import torch
+    n, k, P, seed = sum(sizes), len(sizes), 299, 5
+    D = np.full((n, n), c, dtype=np.float32)
+    np.fill_diagonal(D, 0.0)
+    base = synth.base_labels(sizes)
+    ref = oracle.permanova(D, base, P, seed)
+    assert ref["p"] == 1.0
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res, sw = res.cpu().numpy(), sw.cpu().numpy()
+    assert res[1] == 1.0, (res[1], rechecked)
+    assert max_rel(sw, np.full(P + 1, ref["sW_obs"])) <= 1e-12
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-9
 
 
 # The library keeps its state (stream, workspace, flags, form) per host

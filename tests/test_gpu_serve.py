@@ -104,6 +104,31 @@ def test_executor_warmup_leaves_nothing_behind(ps):
         ex.close()
 
 
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16"])
+def test_jobs_count_ties_like_the_oracle(ps, path):
+    # two equal groups at n = 12 (seed 12 reaches the observed partition
+    # under swapped labels) and a constant matrix with inexact weights:
+    # a served job's p equals the oracle's, ties counted at the tolerance
+    import torch
+    from paper_2505_04556_amd.serve import Request
+    const = np.full((300, 300), 0.3, dtype=np.float32)
+    np.fill_diagonal(const, 0.0)
+    cases = [(synth.uniform_matrix(12, 52), [6, 6], 999, 12),
+             (synth.uniform_matrix(20, 60), [10, 10], 999, 12),
+             (const, [60, 100, 140], 299, 5)]
+    reqs = [Request(id=i, n=D.shape[0], k=len(sizes), grouping=synth.base_labels(sizes),
+                    n_perms=P, seed=seed, arrival=0.0,
+                    make_matrix=(lambda dev, D=D: torch.from_numpy(D).to(dev)))
+            for i, (D, sizes, P, seed) in enumerate(cases)]
+    res, _ = serve(reqs, path=path, round_work=4e6)
+    for r, (D, sizes, P, seed) in zip(reqs, cases):
+        o = res["outcomes"][r.id]
+        assert o.error is None, o.error
+        ref = oracle.permanova(D, synth.base_labels(sizes), P, seed)
+        assert o.result[1] == ref["p"], (r.id, o.result[1], ref["p"])
+        assert max_rel(o.sW_all[1:], ref["sW_perm"]) <= 1e-5
+
+
 @pytest.mark.slow
 def test_serving_trace_matches_oracle_on_a_subset(ps):
     """The 64-request serving trace (n in 1k..20k, k in 2..12, 999 or 9,999

@@ -80,20 +80,52 @@ def test_object_reordering_invariance():
 
 
 # --- P5: constant off-diagonal distance ------------------------------------
-def test_constant_matrix_closed_form_and_ties():
-    sizes = [8, 16, 32, 8]                # powers of two: every weight exact
-    n, k, c = sum(sizes), len(sizes), 0.5
+@pytest.mark.parametrize("sizes,c", [([8, 16, 32, 8], 0.5), ([60, 100, 140], 0.5),
+                                     ([3, 5, 7, 11], 0.3)])
+def test_constant_matrix_closed_form_and_ties(sizes, c):
+    n, k = sum(sizes), len(sizes)
     D = np.full((n, n), c, dtype=np.float32)
     np.fill_diagonal(D, 0.0)
     base = synth.base_labels(sizes)
     perms = oracle.permute(base, 50, seed=77)
     s = oracle.sW(D, np.vstack([base, perms]), weights(sizes))
-    # sum_g w_g n_g (n_g - 1)/2 * c^2 = c^2 (n - k)/2 for w_g = 1/n_g
-    assert np.all(s == c * c * (n - k) / 2)
-    # every permutation ties with the observed grouping, so p = 1
+    # sum_g w_g n_g (n_g - 1)/2 * c^2 = c^2 (n - k)/2 for w_g = 1/n_g, the same
+    # for every grouping with these sizes
+    c2 = float(np.float32(c)) ** 2
+    assert rel(s[0], c2 * (n - k) / 2) < 1e-15
+    if sizes == [8, 16, 32, 8]:          # powers of two: every weight exact
+        assert s[0] == c2 * (n - k) / 2
+    # equal in exact arithmetic, so equal here whatever the sizes: every
+    # within-group sum adds the same n_g (n_g - 1)/2 equal terms
+    assert np.all(s == s[0])
     f = oracle.F(s, oracle.sT(D), n, k)
-    assert oracle.pvalue(f[0], f[1:]) == 1.0
-    assert oracle.pvalue_sW(s[0], s[1:]) == 1.0
+    assert oracle.pvalue_F(f[0], f[1:]) == 1.0
+    assert oracle.pvalue(s[0], s[1:], rtol=0.0) == 1.0
+    assert oracle.pvalue(s[0], s[1:]) == 1.0
+
+
+# --- the same partition under other labels gives the same bits --------------
+@pytest.mark.parametrize("n,half", [(12, 6), (20, 10)])
+def test_swapped_labels_tie_exactly(n, half):
+    D = rand_sym(n, 40 + n)
+    base = synth.base_labels([half, half])
+    w = weights([half, half])
+    perms = oracle.permute(base, 999, seed=12)
+    s = oracle.sW(D, np.vstack([base, 1 - base, perms]), w)
+    assert s[0] == s[1]
+    # every permutation that reproduces the observed partition (under either
+    # labelling) has exactly the observed value and counts as a tie
+    same = np.array([np.array_equal(p, base) or np.array_equal(p, 1 - base) for p in perms])
+    assert np.all(s[2:][same] == s[0])
+    # partitions are 462 (n = 12) or 92,378 (n = 20): distinct values elsewhere
+    # differ from the observed one by far more than the tie tolerance
+    other = s[2:][~same]
+    assert np.all(np.abs(other - s[0]) > 1e-6 * s[0])
+    p = oracle.pvalue(s[0], s[2:])
+    assert p == oracle.pvalue(s[0], s[2:], rtol=0.0)
+    assert p == (1 + np.sum(s[2:] <= s[0])) / 1000
+    if n == 12:
+        assert same.sum() >= 1           # the seed hits the observed partition
 
 
 # --- P6: Euclidean distances: Huygens/Koenig decomposition -----------------
@@ -130,7 +162,13 @@ def test_enumeration_mean_and_submatrix_formula():
     f = oracle.F(s, oracle.sT(D), n, k)
     obs = 0
     count = sum(1 for v in f if v >= f[obs])
-    assert oracle.pvalue(f[obs], f) == (1 + count) / (1 + len(f))
+    assert oracle.pvalue_F(f[obs], f) == (1 + count) / (1 + len(f))
+    # groupings of the same partition (relabelings within equal-size groups)
+    # give identical bits: each partition's value appears exactly as often as
+    # the partition's relabelings (2! for the two groups of size 2)
+    vals, counts = np.unique(s, return_counts=True)
+    assert len(vals) == math.factorial(n) // (math.factorial(2) ** 2 * math.factorial(3) * 2)
+    assert np.all(counts == 2 * 2 * 2 * 6)
 
 
 # --- P8: dyadic inputs: the FP64 result is the exact rational --------------
@@ -152,21 +190,62 @@ def test_dyadic_exact_against_fractions():
         assert Fraction(s[p]) == exact
 
 
-# --- P9: Algorithm 1 order == Algorithm 2 tiled order == dense product ------
-@pytest.mark.parametrize("tile", [1, 3, 7, 64, 500])
-def test_algorithm2_and_dense_formulation(tile):
+# --- P9: brute force over all pairs, and a dense matrix product ------------
+def test_brute_force_pairs():
+    # the statistic's defining sum, term by term over i < j, in exact rationals
+    n, sizes = 23, [5, 7, 11]
+    D = rand_sym(n, 3)
+    w = weights(sizes)
+    perms = oracle.permute(synth.base_labels(sizes), 4, seed=19)
+    s = oracle.sW(D, perms, w)
+    for p in range(perms.shape[0]):
+        g = perms[p]
+        exact = Fraction(0)
+        for i in range(n):
+            for j in range(i + 1, n):
+                if g[i] == g[j]:
+                    exact += Fraction(float(D[i, j])) ** 2 * Fraction(float(w[g[i]]))
+        assert abs(Fraction(s[p]) - exact) <= exact * Fraction(1, 2 ** 50)
+
+
+def test_dense_formulation():
     n, sizes = 500, [60, 140, 300]
     D = rand_sym(n, 31)
     perms = oracle.permute(synth.base_labels(sizes), 5, seed=8)
     w = weights(sizes)
     a1 = oracle.sW(D, perms, w)
-    a2 = oracle.sW_tiled(D, perms, w, tile)
     D2 = D.astype(np.float64) ** 2
     for p in range(perms.shape[0]):
         G = np.eye(3)[perms[p]]                     # n x k one-hot
         dense = 0.5 * float(np.sum(w * np.diag(G.T @ D2 @ G)))
         assert rel(a1[p], dense) < 1e-13
-        assert rel(a2[p], a1[p]) < 1e-13
+
+
+def test_row_blocks_make_up_the_whole():
+    n, sizes = 301, [100, 201]
+    D = rand_sym(n, 6)
+    g = oracle.permute(synth.base_labels(sizes), 7, seed=4)
+    w = weights(sizes)
+    sums = oracle.new_group_sums(g.shape[0], 2)
+    acc = np.zeros(2)
+    for r0 in range(0, n, 37):
+        oracle.group_sums(D[r0:r0 + 37], r0, n, g, sums)
+        oracle.sq_sum(D[r0:r0 + 37], r0, n, acc)
+    assert np.array_equal(oracle.sW_from_sums(sums, w), oracle.sW(D, g, w))
+    assert acc.sum() / n == oracle.sT(D)
+
+
+def test_sums_are_compensated():
+    # one pair at d = 2^26 (d^2 = 2^52, where the FP64 spacing is 1) and 44
+    # pairs at d = 1/2: plain FP64 addition would drop every 1/4; the exact
+    # total 2^52 + 11 is representable and must come out exactly
+    n = 10
+    D = np.full((n, n), 0.5, dtype=np.float32)
+    np.fill_diagonal(D, 0.0)
+    D[0, 1] = D[1, 0] = 2.0 ** 26
+    s = oracle.sW(D, np.zeros(n, dtype=np.int32), [1.0])[0]
+    assert s == 2.0 ** 52 + 11
+    assert oracle.sT(D) * n == 2.0 ** 52 + 11
 
 
 # --- only the strict upper triangle is read --------------------------------
@@ -179,7 +258,6 @@ def test_reads_strict_upper_triangle_only():
     E = D.copy()
     E[np.tril_indices(n)] = np.nan                 # lower triangle and diagonal
     assert np.array_equal(oracle.sW(E, g, w), ref)
-    assert np.array_equal(oracle.sW_tiled(E, g, w, 16), oracle.sW_tiled(D, g, w, 16))
     assert oracle.sT(E) == oracle.sT(D)
 
 
@@ -188,12 +266,20 @@ def test_pvalue_monotone_equivalence():
     n, sizes = 200, [50, 70, 80]
     D = rand_sym(n, 17)
     r = oracle.permanova(D, synth.base_labels(sizes), 199, seed=5)
-    p_sw = oracle.pvalue_sW(r["sW_obs"], r["sW_perm"])
-    assert r["p"] == p_sw
+    assert r["p"] == r["p_F"]
+    assert r["p"] == oracle.pvalue(r["sW_obs"], r["sW_perm"], rtol=0.0)
     assert any(abs(r["p"] * 200 - m) < 1e-9 for m in range(1, 201))
     # F strictly decreasing in s_W
     order = np.argsort(r["sW_perm"])
     assert np.all(np.diff(r["F_perm"][order]) <= 0)
+
+
+def test_pvalue_tie_tolerance():
+    obs = 4.0
+    perm = np.array([4.0 * (1 + 5e-11), 4.0 * (1 + 2e-10), 3.0, 5.0, 4.0])
+    assert oracle.pvalue(obs, perm, rtol=0.0) == 3 / 6          # 3.0 and 4.0
+    assert oracle.pvalue(obs, perm) == 4 / 6                    # + the 5e-11 one
+    assert oracle.pvalue(obs, perm, rtol=1e-9) == 5 / 6
 
 
 # --- P11: linearity in the weights; within + between = total ---------------
@@ -226,8 +312,9 @@ def test_hand_example_sW_sT_F():
 
 
 def test_pvalue_counts_and_degenerate_cases():
+    assert oracle.pvalue_F(2.0, [1.0, 2.0, 3.0, np.nan]) == 3 / 5
     assert oracle.pvalue(2.0, [1.0, 2.0, 3.0, np.nan]) == 3 / 5
-    assert oracle.pvalue_sW(2.0, [1.0, 2.0, 3.0, np.nan]) == 3 / 5
+    assert math.isnan(oracle.pvalue_F(1.0, np.array([], dtype=np.float64)))
     assert math.isnan(oracle.pvalue(1.0, np.array([], dtype=np.float64)))
     assert np.isnan(oracle.F([1.0], 2.0, 10, 1)[0])       # k = 1
     assert np.isnan(oracle.F([1.0], 2.0, 5, 5)[0])        # k = n
@@ -242,6 +329,30 @@ def test_splitmix64_known_answers():
            open(__file__.replace("test_oracle_pins.py", "golden/splitmix64_seed0.txt"))
            if line.strip() and not line.startswith("#")]
     assert oracle.splitmix64_stream(0, len(kat)) == kat
+
+
+def _kat():
+    return [int(line.split()[0], 16) for line in
+            open(__file__.replace("test_oracle_pins.py", "golden/splitmix64_seed0.txt"))
+            if line.strip() and not line.startswith("#")]
+
+
+GAMMA = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+
+
+def test_stream_start_composes_published_outputs():
+    # Permutation p's stream starts at mix(seed XOR mix(p + 1)), mix being the
+    # SplitMix64 output function.  The published outputs for state 0 are
+    # mix(gamma), mix(2 gamma), mix(3 gamma), so choosing p + 1 = j gamma and
+    # seed = mix(j gamma) XOR (j + 1) gamma makes the start mix((j + 1) gamma):
+    # the next published value.  A slip in the mixing constants or shifts, in
+    # the p + 1, or in the order of the two mixes breaks these.
+    kat = _kat()
+    for j in (1, 2):
+        seed = kat[j - 1] ^ (((j + 1) * GAMMA) & M64)
+        p = ((j * GAMMA) - 1) & M64
+        assert oracle.stream_start(seed, p) == kat[j]
 
 
 def test_bounded_power_of_two_is_top_bits():
@@ -263,6 +374,33 @@ def test_bounded_uniform_with_rejection_range():
     assert chi2 < 40                             # 11 dof, p ~ 1e-4
 
 
+@pytest.mark.parametrize("q,b", [(3, 30), (5, 29), (7, 29)])
+def test_bounded_rejection_closed_form(q, b):
+    # s = q 2^b (q odd, q < 2^(32-b)): the low word of x s is (q x mod 2^(32-b)) 2^b
+    # and 2^32 mod s = (2^(32-b) mod q) 2^b, so Lemire's method rejects exactly
+    # the x with q x mod 2^(32-b) < 2^(32-b) mod q and otherwise returns
+    # floor(q x / 2^(32-b)).  The expected sequence follows from the raw
+    # SplitMix64 outputs alone (pinned by the published values).
+    s = q << b
+    r = 1 << (32 - b)
+    st = 0x0DDB_1A5E_5BAD_5EED
+    raw = [x >> 32 for x in oracle.splitmix64_stream(st, 4000)]
+    expect = [(q * x) >> (32 - b) for x in raw if (q * x) % r >= r % q]
+    got = oracle.bounded(st, s, len(expect))
+    assert got == expect
+    assert len(expect) < len(raw)                # some draws were rejected
+
+
+def test_bounded_rejection_removes_residue_bias():
+    # At s = 3 2^30 the top 32-bit word alone (x -> floor(3x/4)) would give the
+    # residues 0, 1, 2 mod 3 with probabilities 1/2, 1/4, 1/4; the rejection
+    # step makes them uniform.  Chi-square with 2 degrees of freedom.
+    v = np.array(oracle.bounded(0x5EED_0003, 3 << 30, 30000), dtype=np.int64)
+    counts = np.bincount(v % 3, minlength=3)
+    chi2 = float(((counts - 10000.0) ** 2 / 10000.0).sum())
+    assert chi2 < 13.8                           # p = 1e-3; without rejection ~3,400
+
+
 def test_permutations_are_uniform_shuffles():
     base = np.array([0, 1, 2, 3], dtype=np.int32)
     P = 24000
@@ -273,6 +411,28 @@ def test_permutations_are_uniform_shuffles():
     assert len(counts) == 24
     chi2 = ((counts - 1000.0) ** 2 / 1000.0).sum()
     assert chi2 < 60                             # 23 dof, p ~ 5e-5
+
+
+def test_durstenfeld_order_on_three_objects():
+    # three objects: the first draw picks the partner of position 2 from
+    # [0, 3), the second the partner of position 1 from [0, 2), each from
+    # permutation p's own stream (draw values pinned above)
+    base = np.array([10, 11, 12], dtype=np.int32)
+    seed = 77
+    got = oracle.permute(base, 6, seed)
+    for p in range(6):
+        st = oracle.stream_start(seed, p)
+        j2 = oracle.bounded(st, 3, 1)[0]
+        raw = oracle.splitmix64_stream(st, 8)
+        # the draws after the first accepted one continue the same stream
+        k = 1
+        while ((3 * (raw[k - 1] >> 32)) & M64) % (1 << 32) < (1 << 32) % 3:
+            k += 1                               # rejected first draws (rare)
+        j1 = (raw[k] >> 32) >> 31                # s = 2 never rejects: the top bit
+        a = [10, 11, 12]
+        a[2], a[j2] = a[j2], a[2]
+        a[1], a[j1] = a[j1], a[1]
+        assert got[p].tolist() == a
 
 
 def test_permutation_multiset_and_stream_independence():
