@@ -140,6 +140,28 @@ int pstat_sW(const float *mat, int64_t n, const int32_t *groupings, int64_t n_pe
 int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
                int32_t n_groups, const double *inv_group_sizes, double *out);
 
+/* pstat_sW_k for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or other allocating routine; its scratch is a
+ * static device array of pstat_noalloc_scratch_bytes() bytes (64 MiB), one
+ * per device, reserved when the library's code is loaded on that device and
+ * held until the process ends; the thread's workspace (pstat_set_workspace)
+ * is not used.  Same arguments, results and asynchronous label check as
+ * pstat_sW_k, on the thread's form, layout and stream (pstat_profile does not
+ * time it).  *scratch_bytes (host, may be NULL) receives the scratch the
+ * shape needs; a shape needing more than the array gives PSTAT_ENOMEM before
+ * any launch, with out untouched.  Every call on one device shares that
+ * device's array: calls that overlap on one device (two threads, or two
+ * streams without ordering between them) race and give wrong results; calls
+ * ordered on one stream are safe (each call writes before it reads every
+ * byte of scratch it uses, so nothing left by an earlier call is read). */
+int pstat_sW_k_noalloc(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+                       int32_t n_groups, const double *inv_group_sizes, double *out,
+                       size_t *scratch_bytes);
+
+/* Size of pstat_sW_k_noalloc's static scratch array, bytes. */
+size_t pstat_noalloc_scratch_bytes(void);
+
 /* PSTAT_OK if no out-of-range label was seen by this thread's pstat_sW_k calls
  * since the previous check, else PSTAT_ELABEL.  Synchronises the stream. */
 int pstat_check_labels(void);

@@ -83,6 +83,8 @@ _SIGS = {
     "pstat_workspace_bytes": ([_i64, _i64, _i32, _int], _size),
     "pstat_sW": ([_P, _i64, _P, _i64, _P, _P], _int),
     "pstat_sW_k": ([_P, _i64, _P, _i64, _i32, _P, _P], _int),
+    "pstat_sW_k_noalloc": ([_P, _i64, _P, _i64, _i32, _P, _P, ctypes.POINTER(_size)], _int),
+    "pstat_noalloc_scratch_bytes": ([], _size),
     "pstat_check_labels": ([], _int),
     "pstat_sT": ([_P, _i64, _P], _int),
     "pstat_F": ([_P, _i64, _P, _i64, _i32, _P], _int),
@@ -273,6 +275,26 @@ def pstat_sW_k(mat, groupings, n_groups: int, inv_group_sizes, out=None) -> torc
                            _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
                            _dev(out, torch.float64, "out")))
     return out
+
+
+def pstat_sW_k_noalloc(mat, groupings, n_groups: int, inv_group_sizes, out) -> int:
+    """pstat_sW_k with the library's static scratch (allocates nothing; out
+    must be given).  Returns the scratch bytes the shape used."""
+    P = _rows(groupings, _mat_n(mat))
+    _need(inv_group_sizes, int(n_groups), "inv_group_sizes")
+    _need(out, P, "out")
+    _ready(mat.device)
+    mp, n = _mat(mat)
+    used = _size(0)
+    _check(_lib.pstat_sW_k_noalloc(mp, n, _dev(groupings, torch.int32, "groupings"), P,
+                                   int(n_groups),
+                                   _dev(inv_group_sizes, torch.float64, "inv_group_sizes"),
+                                   _dev(out, torch.float64, "out"), ctypes.byref(used)))
+    return int(used.value)
+
+
+def pstat_noalloc_scratch_bytes() -> int:
+    return int(_lib.pstat_noalloc_scratch_bytes())
 
 
 def pstat_check_labels() -> None:

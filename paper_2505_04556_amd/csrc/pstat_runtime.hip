@@ -17,6 +17,14 @@ namespace rt {
 
 thread_local Thread tls;  // declared in runtime.h
 
+// Scratch of pstat_sW_k_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  Host code never uses this name as an
+// address (on the host it is only a stand-in for the symbol): pstat_init
+// takes each device's address with hipGetSymbolAddress and keeps it in
+// DeviceInfo::static_scratch.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_devices;
 
@@ -426,6 +434,11 @@ int pstat_init(int device) {
             if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
                     hipSuccess && v > 0)
                 d.lds_limit = (size_t)v;
+            // this device is current: its own copy of the static scratch
+            void *addr = nullptr;
+            const hipError_t se = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (se != hipSuccess || !addr) return hip_fail(se, "hipGetSymbolAddress(scratch)");
+            d.static_scratch = (char *)addr;
             d.ready = true;
         }
     }
@@ -522,6 +535,40 @@ int pstat_sW_k(const float *mat, int64_t n, const int32_t *groupings, int64_t n_
     return sW_common(mat, n, groupings, n_perms, n_groups, inv_group_sizes, out, false, nullptr,
                      tls.path, tls.packed);
 }
+
+int pstat_sW_k_noalloc(const float *mat, int64_t n, const int32_t *groupings, int64_t n_perms,
+                       int32_t n_groups, const double *inv_group_sizes, double *out,
+                       size_t *scratch_bytes) {
+    int rc = need_init();
+    if (rc) return rc;
+    if (n < 2) return fail(PSTAT_EINVAL, "n must be >= 2 (got %lld)", (long long)n);
+    if (n_perms < 0) return fail(PSTAT_EINVAL, "n_perms must be >= 0");
+    if (n_groups < 1 || n_groups > kMaxGroups)
+        return fail(PSTAT_EINVAL, "n_groups must be in [1, %d]", kMaxGroups);
+    const int path = resolve_path(tls.path, n, n_groups);
+    const size_t need = sW_bytes(n, n_perms, n_groups, path, true);
+    if (scratch_bytes) *scratch_bytes = need;
+    if (n_perms == 0) return PSTAT_OK;
+    if (need > kStaticScratchBytes)
+        return fail(PSTAT_ENOMEM,
+                    "this shape needs %zu bytes of scratch, beyond the %zu-byte static scratch "
+                    "of pstat_sW_k_noalloc (use pstat_sW_k)",
+                    need, kStaticScratchBytes);
+    if ((rc = check_dev_ptr(mat, "mat"))) return rc;
+    if ((rc = check_dev_ptr(groupings, "groupings"))) return rc;
+    if ((rc = check_dev_ptr(inv_group_sizes, "inv_group_sizes"))) return rc;
+    if ((rc = check_dev_ptr(out, "out"))) return rc;
+    char *base = dev_info().static_scratch;
+    if (!base) return fail(PSTAT_ESTATE, "no static scratch on device %d", tls.device);
+    Carver c{base, kStaticScratchBytes, 0, false};
+    SwLayout L;
+    layout_sW(c, n, n_perms, n_groups, path, true, L);
+    // untimed: the event pairs of pstat_profile would be created here
+    return exec_sW(L, mat, n, groupings, nullptr, n_perms, n_groups, n_groups, inv_group_sizes,
+                   out, nullptr, tls.flags, false, nullptr, nullptr, false, nullptr, tls.packed);
+}
+
+size_t pstat_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 
 int pstat_check_labels(void) {
     int rc = need_init();

@@ -24,6 +24,9 @@ struct DeviceInfo {
     bool ready = false;
     int n_cu = 256;
     size_t lds_limit = 65536;
+    // this device's copy of the static scratch array of pstat_sW_k_noalloc
+    // (its device address, from hipGetSymbolAddress at pstat_init)
+    char *static_scratch = nullptr;
 };
 
 struct Thread {
