@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_count_rejections.argtypes = [i64, i64, u64]
         L.oracle_count_rejections.restype = i64
         L.oracle_max_threads.restype = c_int
+        L.oracle_pin_threads.argtypes = [P, c_int, c_int, c_int]
+        L.oracle_pin_threads.restype = c_int
         _lib = L
     return _lib
 
@@ -118,6 +120,14 @@ def _weights(inv, k: int) -> np.ndarray:
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+def pin_threads(cpus, nthreads: int, one_each: bool) -> None:
+    """CPU affinity of a team of nthreads (measurement helper): thread t on
+    cpus[t] alone (one_each), else every thread on all of cpus."""
+    arr = np.ascontiguousarray(cpus, dtype=np.int32)
+    if lib().oracle_pin_threads(_ptr(arr), arr.shape[0], int(nthreads), int(bool(one_each))):
+        raise OSError("sched_setaffinity failed")
 
 
 def sW(mat, groupings, inv, nthreads: int = 0, k: int | None = None) -> np.ndarray:

@@ -44,7 +44,9 @@
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC
  */
+#define _GNU_SOURCE
 #include <math.h>
+#include <sched.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -55,6 +57,29 @@ static void set_threads(int nthreads) {
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* Measurement helper of the CPU baseline, no part of any statistic: sets the
+ * CPU affinity of the threads of a team of `nthreads` (the same threads later
+ * parallel regions of that size reuse).  With one_each (and ncpus >= nthreads)
+ * thread t runs on cpus[t] alone; otherwise every thread may run on all ncpus
+ * CPUs (to undo a pinning).  Returns 0, or -1 if a call failed. */
+int oracle_pin_threads(const int *cpus, int ncpus, int nthreads, int one_each) {
+    int bad = 0;
+    if (one_each && ncpus < nthreads) return -1;
+    omp_set_num_threads(nthreads);
+#pragma omp parallel num_threads(nthreads) reduction(| : bad)
+    {
+        cpu_set_t set;
+        CPU_ZERO(&set);
+        if (one_each) {
+            CPU_SET(cpus[omp_get_thread_num()], &set);
+        } else {
+            for (int c = 0; c < ncpus; c++) CPU_SET(cpus[c], &set);
+        }
+        if (sched_setaffinity(0, sizeof(set), &set) != 0) bad = 1;
+    }
+    return bad ? -1 : 0;
+}
 
 /* ---------------------------------------------------------------------------
  * Compensated summation (Neumaier 1974): *hi + *lo carries the running sum.

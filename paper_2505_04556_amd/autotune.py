@@ -12,7 +12,10 @@ The search space is the one the C ABI exposes through ``pstat_set_tuning``:
   (256 or 512).
 
 Timings are the main kernel's own duration (HIP events through
-``pstat_profile``), median of ``reps`` runs after a warm-up.  The form chosen
+``pstat_profile``), median of ``reps`` runs after a warm-up; for the plain
+kernels the entry also records the fraction of the 8 TB/s HBM peak that the
+algorithmic matrix traffic (the strict upper triangle once per batch of
+permutations) reaches at that time.  The form chosen
 for ``auto`` is the fastest of those that meet the 1e-5 relative accuracy bar
 (plain FP32 and split BF16); BF16 and FP16 are tuned too but never chosen
 automatically.
@@ -36,6 +39,7 @@ import paper_2505_04556_amd as ps
 PLAIN_SPACE = [(t, b) for t in (32, 64) for b in (64, 128, 256)]
 MFMA_SPACE = [(kc, nc) for kc in (512, 1024, 2048, 4096) for nc in (256, 512)]
 ACCURATE = ("plain_f32", "mfma_split_bf16", "mfma_split3_bf16")
+PEAK_HBM_BYTES_S = 8e12   # MI355X HBM3E
 ALL_PATHS = ("plain_f32", "mfma_split_bf16", "mfma_bf16", "mfma_f16")
 
 
@@ -115,9 +119,14 @@ def tune(mat: torch.Tensor, groupings: torch.Tensor, n_groups: int, inv: torch.T
             except ps.PstatError as e:     # e.g. a workspace that does not fit
                 trials.append({"tile": tile, "batch": batch, "error": str(e)})
                 continue
-            trials.append({"tile": tile, "batch": batch, "kernel_ms": ms})
+            t = {"tile": tile, "batch": batch, "kernel_ms": ms}
+            if path.startswith("plain"):
+                # the strict upper triangle streams once per `batch` permutations
+                passes = -(-P // batch)
+                t["hbm_frac"] = 4.0 * n * (n - 1) / 2 * passes / (ms * 1e-3) / PEAK_HBM_BYTES_S
+            trials.append(t)
             if best is None or ms < best["kernel_ms"]:
-                best = {"tile": tile, "batch": batch, "kernel_ms": ms}
+                best = dict(t)
         ps.pstat_set_tuning(path, 0, 0)
         if best is not None:
             entry["paths"][path] = dict(best, trials=trials)
