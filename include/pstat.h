@@ -207,8 +207,8 @@ int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed
  * weights 1/n_g from `grouping` (n_groups groups), n_perms shuffles
  * (pstat_permute with `seed`), s_W of the observed grouping and of every
  * shuffle, s_T, F and p (as pstat_pvalue, ties at PSTAT_TIE_RTOL).  The
- * observed grouping and the first 15 shuffles are recomputed in FP64; the
- * largest relative error of the form over those 16, times 16, is the band
+ * observed grouping and the first 7 shuffles are recomputed in FP64; the
+ * largest relative error of the form over those 8, times 16, is the band
  * (at least 1e-13): every shuffle whose s_W lies within the band of the
  * p-value's edge (from the observed value to PSTAT_TIE_RTOL above it) is
  * recomputed in FP64 too before counting.  The band is measured, not a

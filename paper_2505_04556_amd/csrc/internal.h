@@ -161,7 +161,7 @@ __device__ inline int f16_scale_exp(uint32_t maxabs_bits) {
 // FP64 s_W of rows 0 .. m-1 (m <= kRecheckRows) of a staged u16 label table
 // (rows of `stride` entries), computed inside the MFMA pre-pass; part holds
 // prepass_blocks(n) * kRecheckRows doubles, out[q] receives row q's s_W.
-constexpr int kRecheckRows = 16;
+constexpr int kRecheckRows = 8;
 struct PrepassRecheck {
     const uint16_t *lab = nullptr;
     int64_t stride = 0;

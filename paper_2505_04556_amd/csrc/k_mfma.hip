@@ -37,6 +37,8 @@
 // relative to s_W.
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "lane_mask.h"
 
@@ -127,6 +129,69 @@ __device__ inline void unit_sums(const float (*sm)[kKBlock + 1], double *__restr
     if (c4 == 0) out[128 + cc] = b;
 }
 
+// Loads of one unit into registers: thread t reads rows 16 ps + t / 16
+// (ps < 8) at the four columns 4 (t % 16) .. + 3 of the block, 0 outside the
+// matrix; with RC also 8 row labels of grouping t / 16 (t < 16 Q) and, for
+// t < 8 Q, 8 column labels of grouping t / 8 (16-byte reads; the staged label
+// rows are padded to a multiple of 128 entries, so these reads stay inside
+// them).
+struct PrepassLoads {
+    float d[8][4];
+    uint4 lr, lc;
+};
+
+template <bool RC, int Q>
+__device__ __attribute__((always_inline)) inline void prepass_fetch(
+    const float *__restrict__ mat, int64_t n, int64_t kb_total, int vec, int packed,
+    const PrepassRecheck &rc, int64_t unit, int tid, PrepassLoads &L) {
+    const int64_t I = unit_panel(unit, kb_total);
+    const int64_t kb = 2 * I + (unit - I * (kb_total - I + 1));
+    const int64_t r0 = I * kPanel, c0 = kb * kKBlock;
+    const int cq = (tid % 16) * 4, rq = tid / 16;
+    // blocks inside the square layout need no per-element test (the same
+    // answer for the whole work-group)
+    if (vec && r0 + kPanel <= n && c0 + kKBlock <= n) {
+        const float *base = mat + (uint64_t)(r0 + rq) * (uint64_t)n + (c0 + cq);
+#pragma unroll
+        for (int ps = 0; ps < 8; ps++) {
+            const float4 v = *reinterpret_cast<const float4 *>(base + (uint64_t)(16 * ps) * n);
+            L.d[ps][0] = v.x;
+            L.d[ps][1] = v.y;
+            L.d[ps][2] = v.z;
+            L.d[ps][3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int ps = 0; ps < 8; ps++) {
+            const int64_t i = r0 + ps * 16 + rq, j0 = c0 + cq;
+            if (vec && i < n && j0 + 3 < n) {
+                const float4 v =
+                    *reinterpret_cast<const float4 *>(mat + (uint64_t)i * (uint64_t)n + j0);
+                L.d[ps][0] = v.x;
+                L.d[ps][1] = v.y;
+                L.d[ps][2] = v.z;
+                L.d[ps][3] = v.w;
+            } else {
+                // (the packed layout has no entries at j <= i)
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    L.d[ps][e] = (i < n && j0 + e < n && (!packed || j0 + e > i))
+                                     ? mat[d_index(i, j0 + e, n, packed)]
+                                     : 0.0f;
+            }
+        }
+    }
+    L.lr = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    L.lc = L.lr;
+    if constexpr (RC) {
+        const int qr = tid / 16, qc = tid / 8;
+        if (qr < rc.m)
+            L.lr = *reinterpret_cast<const uint4 *>(rc.lab + qr * rc.stride + r0 + (tid % 16) * 8);
+        if (tid < 8 * Q && qc < rc.m)
+            L.lc = *reinterpret_cast<const uint4 *>(rc.lab + qc * rc.stride + c0 + (tid % 8) * 8);
+    }
+}
+
 template <int DT, bool RC>
 __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, int64_t n,
                                                  int64_t kb_total, int64_t comp_units, int vec,
@@ -158,36 +223,8 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
         const int64_t I = unit_panel(unit, kb_total);
         const int64_t kb = 2 * I + (unit - I * (kb_total - I + 1));
         const int64_t r0 = I * kPanel, c0 = kb * kKBlock;
-        float d[8][4];
-#pragma unroll
-        for (int ps = 0; ps < 8; ps++) {
-            const int64_t i = r0 + ps * 16 + rq, j0 = c0 + cq;
-            if (vec && i < n && j0 + 3 < n) {
-                const float4 v = *reinterpret_cast<const float4 *>(mat + (uint64_t)i * (uint64_t)n + j0);
-                d[ps][0] = v.x;
-                d[ps][1] = v.y;
-                d[ps][2] = v.z;
-                d[ps][3] = v.w;
-            } else {
-                // (the packed layout has no entries at j <= i)
-#pragma unroll
-                for (int e = 0; e < 4; e++)
-                    d[ps][e] = (i < n && j0 + e < n && (!packed || j0 + e > i))
-                                   ? mat[d_index(i, j0 + e, n, packed)]
-                                   : 0.0f;
-            }
-        }
-        // recheck labels of the unit: thread t loads 8 row labels of grouping
-        // t / 16 and, for t < 128, 8 column labels of grouping t / 8 (16-byte
-        // reads; the staged rows are padded to a multiple of 128 entries)
-        uint4 lr = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), lc = lr;
-        if constexpr (RC) {
-            const int qr = tid / 16, qc = tid / 8;
-            if (qr < rc.m)
-                lr = *reinterpret_cast<const uint4 *>(rc.lab + qr * rc.stride + r0 + (tid % 16) * 8);
-            if (tid < 128 && qc < rc.m)
-                lc = *reinterpret_cast<const uint4 *>(rc.lab + qc * rc.stride + c0 + (tid % 8) * 8);
-        }
+        PrepassLoads cur;
+        prepass_fetch<RC, Q>(mat, n, kb_total, vec, packed, rc, unit, tid, cur);
         if (rcs && prev >= 0) {
             __syncthreads();   // the previous unit's stored values are in LDS
             unit_sums(sm, rcs + prev * 192, tid);
@@ -195,69 +232,92 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
         prev = unit;
         __syncthreads();   // the previous unit's LDS reads are done
         // squares: FP32 into LDS for the fragments; exact FP64 for s_T and
-        // the recheck (0 off the strict upper triangle)
-        double d2[4][8];
+        // the recheck; 0 off the strict upper triangle.  Only the diagonal
+        // blocks and the matrix's edge need that test, so the work-group
+        // takes one of two versions of this part per unit (EDGE or not): in
+        // block coordinates an entry is kept when row < lim_r, column <
+        // lim_c and column + delta > row.
+        const int lim_r = (int)(n - r0 < kPanel ? n - r0 : kPanel);
+        const int lim_c = (int)(n - c0 < kKBlock ? n - c0 : kKBlock);
+        const int delta = (int)(c0 - r0 < 2 * kPanel ? c0 - r0 : 2 * kPanel);
+        const bool edge = lim_r < kPanel || lim_c < kKBlock || delta < kPanel;
+        auto squares = [&](auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            auto kept = [&](int ps, int e) {
+                const int r = ps * 16 + rq, c = cq + e;
+                return !EDGE || (r < lim_r && c < lim_c && c + delta > r);
+            };
 #pragma unroll
-        for (int ps = 0; ps < 8; ps++) {
-            const int r = ps * 16 + rq;
-            const int64_t i = r0 + r;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int64_t j = c0 + cq + e;
-                const bool keep = i < n && j < n && j > i;
-                const float x = d[ps][e];
-                sm[r][cq + e] = keep ? x * x : 0.0f;
-                const double xx = keep ? (double)x * (double)x : 0.0;
-                st += xx;
-                d2[e][ps] = xx;
-            }
-        }
-        if constexpr (RC) {
-            const uint32_t l8[4] = {lr.x, lr.y, lr.z, lr.w};
-            const int qr = tid / 16, rb = (tid % 16) * 8;
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int r = rb + e;
-                rrow[qr][r % 16][r / 16] = (l8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
-            }
-            if (tid < 128) {
-                const uint32_t c8[4] = {lc.x, lc.y, lc.z, lc.w};
-                const int qc = tid / 8, cb = (tid % 8) * 8;
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    const uint32_t l = (c8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
-                    rcol[qc][cb + e] = l;
-                    rw[qc][cb + e] = (l < (uint32_t)rc.k) ? rc.w[l] : 0.0;
-                }
-            }
-        }
-        __syncthreads();
-        if constexpr (RC) {
-#pragma unroll
-            for (int q = 0; q < Q; q++) {
-                const uint4 ra = *reinterpret_cast<const uint4 *>(&rrow[q][rq][0]);
-                const uint4 rb = *reinterpret_cast<const uint4 *>(&rrow[q][rq][4]);
-                const uint32_t rl[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-                const uint4 cl = *reinterpret_cast<const uint4 *>(&rcol[q][cq]);
-                const double2 w01 = *reinterpret_cast<const double2 *>(&rw[q][cq]);
-                const double2 w23 = *reinterpret_cast<const double2 *>(&rw[q][cq + 2]);
-                const uint32_t cls[4] = {cl.x, cl.y, cl.z, cl.w};
-                const double ws[4] = {w01.x, w01.y, w23.x, w23.y};
+            for (int ps = 0; ps < 8; ps++) {
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    double sum = 0.0;
-                    masked_add8(sum, cls[e], rl, d2[e]);
-                    acc[q] = __builtin_fma(sum, ws[e], acc[q]);
+                    const float x = cur.d[ps][e];
+                    const bool keep = kept(ps, e);
+                    sm[ps * 16 + rq][cq + e] = keep ? x * x : 0.0f;
+                    if constexpr (!RC) st += keep ? (double)x * (double)x : 0.0;
                 }
             }
-        }
+            if constexpr (RC) {
+                const uint32_t l8[4] = {cur.lr.x, cur.lr.y, cur.lr.z, cur.lr.w};
+                const int qr = tid / 16, rb = (tid % 16) * 8;
+                if (qr < Q) {
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const int r = rb + e;
+                        rrow[qr][r % 16][r / 16] = (l8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+                    }
+                }
+                if (tid < 8 * Q) {
+                    const uint32_t c8[4] = {cur.lc.x, cur.lc.y, cur.lc.z, cur.lc.w};
+                    const int qc = tid / 8, cb = (tid % 8) * 8;
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const uint32_t l = (c8[e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+                        rcol[qc][cb + e] = l;
+                        rw[qc][cb + e] = (l < (uint32_t)rc.k) ? rc.w[l] : 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            if constexpr (RC) {
+                // one column at a time: its 8 exact FP64 squares (which also
+                // go into s_T), then every grouping's masked sum of them
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    double d2[8];
+#pragma unroll
+                    for (int ps = 0; ps < 8; ps++) {
+                        const float x = cur.d[ps][e];
+                        d2[ps] = kept(ps, e) ? (double)x * (double)x : 0.0;
+                        st += d2[ps];
+                    }
+#pragma unroll
+                    for (int q = 0; q < Q; q++) {
+                        const uint4 ra = *reinterpret_cast<const uint4 *>(&rrow[q][rq][0]);
+                        const uint4 rb = *reinterpret_cast<const uint4 *>(&rrow[q][rq][4]);
+                        const uint32_t rl[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+                        double sum = 0.0;
+                        masked_add8(sum, rcol[q][cq + e], rl, d2);
+                        acc[q] = __builtin_fma(sum, rw[q][cq + e], acc[q]);
+                        // one grouping's labels live at a time
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+        };
+        if (edge)
+            squares(std::integral_constant<bool, true>{});
+        else
+            squares(std::integral_constant<bool, false>{});
         const int64_t off = unit;
+#pragma unroll
         for (int q = 0; q < 4; q++) {
             const int idx = tid + 256 * q;
             const int rb = idx / 256, s = (idx / 64) % 4, lane = idx % 64;
             const int r = rb * 32 + (lane % 32);
             const int cb = 32 * (lane / 32) + 8 * s;
             uint32_t hw[4], lw[4], tw[4];
+#pragma unroll
             for (int e2 = 0; e2 < 4; e2++) {
                 const float x0 = sm[r][cb + 2 * e2], x1 = sm[r][cb + 2 * e2 + 1];
                 float s0, s1;   // the values the MFMAs will see
@@ -273,9 +333,9 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                     // they share the exponent range); for DT 3 the remainder
                     // is split once more and the last remainder, at most 8
                     // significant bits, is exact in BF16 (normal range)
-                    const float r0 = x0 - bf16_bits_to_float(h0);
-                    const float r1 = x1 - bf16_bits_to_float(h1);
-                    const uint16_t l0 = to_bf16_bits(r0), l1 = to_bf16_bits(r1);
+                    const float r0f = x0 - bf16_bits_to_float(h0);
+                    const float r1f = x1 - bf16_bits_to_float(h1);
+                    const uint16_t l0 = to_bf16_bits(r0f), l1 = to_bf16_bits(r1f);
                     lw[e2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
                     s0 = bf16_bits_to_float(h0);
                     s1 = bf16_bits_to_float(h1);
@@ -284,16 +344,18 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                         s1 += bf16_bits_to_float(l1);
                     }
                     if (DT == 3) {
-                        const uint16_t t0 = to_bf16_bits(r0 - bf16_bits_to_float(l0));
-                        const uint16_t t1 = to_bf16_bits(r1 - bf16_bits_to_float(l1));
+                        const uint16_t t0 = to_bf16_bits(r0f - bf16_bits_to_float(l0));
+                        const uint16_t t1 = to_bf16_bits(r1f - bf16_bits_to_float(l1));
                         tw[e2] = (uint32_t)t0 | ((uint32_t)t1 << 16);
                         s0 += bf16_bits_to_float(t0);
                         s1 += bf16_bits_to_float(t1);
                     }
                 }
                 // each element is read and rewritten by this thread only
-                sm[r][cb + 2 * e2] = s0;
-                sm[r][cb + 2 * e2 + 1] = s1;
+                if (rcs) {
+                    sm[r][cb + 2 * e2] = s0;
+                    sm[r][cb + 2 * e2 + 1] = s1;
+                }
             }
             tiles[off * kUnitU4 + idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             if (DT >= 2)
@@ -796,10 +858,15 @@ void launch_mfma_prepass(const float *mat, int64_t n, int dtype, void *tiles, hi
     if (rc) launch_reduce_partials(rc->part, blocks, kRecheckRows, rc->m, rc->out, s);
 }
 
+// Work-groups of the pre-pass: what stays resident on the device (two
+// per CU), never more than the units or the s_T partial slots.  A function of
+// n alone, so every caller reduces the partials in the same order.
+constexpr int64_t kPrepassBlocks = 512;
 int64_t prepass_blocks(int64_t n) {
     const int64_t panels = ceil_div(n, kPanel);
     const int64_t comp_units = panels * (panels + 1);
-    const int64_t b = sT_partials_count(n);
+    int64_t b = sT_partials_count(n);
+    if (b > kPrepassBlocks) b = kPrepassBlocks;
     return b < comp_units ? b : comp_units;
 }
 

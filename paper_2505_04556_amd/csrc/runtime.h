@@ -175,7 +175,7 @@ int finish_test(const TestHead &h, const float *mat, int64_t n, int32_t k, int64
 // Tie band of the p-value recheck: kBandMargin times the largest relative
 // error of the fast path over the observed grouping and the first
 // kBandSamples permutations (all recomputed in FP64).
-constexpr int64_t kBandSamples = 15;
+constexpr int64_t kBandSamples = 7;
 constexpr double kBandMargin = 16.0;
 
 } // namespace rt
