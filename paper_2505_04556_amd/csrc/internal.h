@@ -187,9 +187,18 @@ void launch_item_table(const MfmaPlan &pl, int32_t *tab, hipStream_t s);
 // tab is scratch for the item table (mfma_table_bytes).  Complement form
 // (pl.cx): z[item][P][k - 1][2], per column the rows of its group and the
 // rows not in group *Lp.
+// lab4: the same labels packed four bits each (launch_pack_nibbles; k <= 15),
+// or NULL to read the u16 table.
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
                 int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s,
-                const int32_t *Lp = nullptr);
+                const int32_t *Lp = nullptr, const uint32_t *lab4 = nullptr);
+// Whether launch_mfma should be given the labels packed four bits each for
+// this plan (k <= 15, and enough permutations per work-group that their u16
+// labels would outweigh the matrix block it copies).
+bool mfma_use_nibbles(const MfmaPlan &pl, int32_t k);
+// out (count / 8 dwords) = the u16 label table lab (count entries, a multiple
+// of 8, every real label below 15) packed four bits per label, padding as 15.
+void launch_pack_nibbles(const uint16_t *lab, int64_t count, uint32_t *out, hipStream_t s);
 
 // ---- complement form (k_reduce.hip) ------------------------------------------
 // Device state of one complement-form evaluation.

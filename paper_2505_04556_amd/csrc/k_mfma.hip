@@ -419,6 +419,25 @@ __global__ __launch_bounds__(256) void k_max_abs_upper(const float *__restrict__
     }
 }
 
+// ---- labels packed four bits each ------------------------------------------------
+// out dword e = the 8 u16 labels e*8 .. e*8+7 of the staged table, label i in
+// bits 4i .. 4i+3 (every label below 15, the padding 0xFFFF becomes 15).
+__global__ __launch_bounds__(256) void k_pack_nibbles(const uint4 *__restrict__ lab,
+                                                      int64_t words, uint32_t *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < words;
+         e += (int64_t)gridDim.x * 256) {
+        const uint4 v = lab[e];
+        const uint32_t h[4] = {v.x, v.y, v.z, v.w};
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t lo = h[q] & 0xFFFFu, hi = h[q] >> 16;
+            w |= ((lo < 15u ? lo : 15u) | ((hi < 15u ? hi : 15u) << 4)) << (8 * q);
+        }
+        out[e] = w;
+    }
+}
+
 // ---- work items ---------------------------------------------------------------
 // tab[3*item] = panel I, tab[3*item+1] = first K block, tab[3*item+2] = end.
 // Items in panel order, K chunks ascending; thread I writes panel I's items
@@ -460,6 +479,31 @@ __device__ inline uint4 onehot8(uint4 L, uint32_t gg) {
     return make_uint4(out[0], out[1], out[2], out[3]);
 }
 
+// The same from 8 labels packed four bits each (label i in bits 4i .. 4i+3):
+// y = labels ^ (g in every nibble) is 0 in exactly the matching nibbles; a
+// byte permute puts byte q (labels 2q, 2q+1) in both 16-bit halves, the mask
+// keeps the low nibble in the low half and the high nibble (times 16) in the
+// high one, and the saturating subtract and multiply follow as above: four
+// VALU operations per dword, and one per eight labels for the xor.
+template <int DT>
+__device__ inline uint4 onehot8_nib(uint32_t L, uint32_t gg) {
+    const uint32_t one1 = 0x00010001u;
+    const uint32_t onev = One<DT>::v | (One<DT>::v << 16);
+    const uint32_t y = L ^ ((gg & 0xFu) * 0x11111111u);
+    uint32_t out[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        // selector bytes: q, zero, q, zero (0x0C selects the constant 0)
+        const uint32_t sel = (uint32_t)q | 0x0C00u | ((uint32_t)q << 16) | 0x0C000000u;
+        const uint32_t v = __builtin_amdgcn_perm(0u, y, sel) & 0x00F0000Fu;
+        uint32_t t, o;
+        asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(t) : "v"(one1), "v"(v));
+        asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(o) : "v"(t), "v"(onev));
+        out[q] = o;
+    }
+    return make_uint4(out[0], out[1], out[2], out[3]);
+}
+
 template <int DT>
 __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
     if (DT == 1)
@@ -489,11 +533,15 @@ __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
 // cx: complement form -- kcol = k - 1 columns per grouping, for the groups
 // other than Lg; the epilogue writes two sums per column (rows of the
 // column's group, rows not in Lg).  Otherwise kcol = k.
-template <int DT, int NF, int LQ>
+// NIB: the labels come from the table packed four bits per label (k <= 15,
+// padding 15): per permutation and K block two 16-byte chunks, no pad
+// chunk; a K step reads one dword (8 labels) instead of 16 bytes.
+template <int DT, int NF, int LQ, bool NIB>
 __device__ __attribute__((always_inline)) inline void mfma_unit(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t item, int64_t nb, const uint16_t *__restrict__ lab,
-    int64_t n_pad, bool cx, int32_t kcol, int32_t Lg, int64_t P, float *__restrict__ z) {
+    const uint32_t *__restrict__ lab4, int64_t n_pad, bool cx, int32_t kcol, int32_t Lg, int64_t P,
+    float *__restrict__ z) {
     constexpr int BT = DT == 1 ? 1 : 0;     // operand type of the MFMA
     constexpr int NC = DT == 3 ? 3 : DT == 2 ? 2 : 1;   // A components (hi, [mid,] lo)
     constexpr int UNIT = NC * kUnitU4;      // uint4 of one staged K block
@@ -502,7 +550,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // one pad chunk (a stride of 9 chunks spreads neighbouring permutations
     // over the LDS banks); LQ * 256 slots hold the (COLS - 1) / k + 2
     // permutations a work-group's columns can touch (the launch picks LQ).
-    constexpr int kLStride = 9;
+    constexpr int kLStride = NIB ? 2 : 9;   // 16-byte slots per permutation
     constexpr int LSLOTS = LQ * 256;
     __shared__ uint4 sA0[UNIT];
     __shared__ uint4 sA1[UNIT];
@@ -528,7 +576,8 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
         if (cx && g >= (uint32_t)Lg) g++;   // the column's group skips Lg
         gg[nf] = g | (g << 16);
         // K step s of a block uses rows 8s + 32*half + 0..7: chunk s + 4*half
-        lslot[nf] = (int)(p - p_lo) * kLStride + 4 * half;
+        // (u16: 16-byte slot; NIB: dword, 8 per permutation)
+        lslot[nf] = NIB ? (int)(p - p_lo) * 8 + 4 * half : (int)(p - p_lo) * kLStride + 4 * half;
     }
 
     f32x16 acc[4][NF];
@@ -550,10 +599,13 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
             const int j = q * 256 + tid;
             const int pr = j / kLStride;
             int ch = j - pr * kLStride;
-            if (ch == kLStride - 1) ch = 0;
+            if (!NIB && ch == kLStride - 1) ch = 0;
             int64_t p = p_lo + pr;
             if (p > p_hi) p = p_hi;
-            const uint16_t *src = lab + p * n_pad + kb * kKBlock + ch * 8;
+            // NIB rows hold n_pad / 2 bytes, 32 per K block
+            const void *src = NIB ? (const void *)((const char *)lab4 + p * (n_pad / 2) +
+                                                   kb * (kKBlock / 2) + ch * 16)
+                                  : (const void *)(lab + p * n_pad + kb * kKBlock + ch * 8);
             __builtin_amdgcn_global_load_lds(
                 (__attribute__((address_space(1))) void *)src,
                 (__attribute__((address_space(3))) void *)&dL[q * 256 + wave * 64], 16, 0, 0);
@@ -577,13 +629,24 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // each A fragment just before its MFMAs, exposing the LDS latency).
     uint4 Ac[4][NC], An[4][NC];
     uint4 Ln[NF], B[NF];
+    uint32_t Lw[NF];
     auto load_step = [&](const uint4 *cA, const uint4 *cL, int s) {
 #pragma unroll
         for (int rb = 0; rb < 4; rb++)
 #pragma unroll
             for (int c = 0; c < NC; c++) An[rb][c] = cA[c * kUnitU4 + (rb * 4 + s) * 64 + lane];
 #pragma unroll
-        for (int nf = 0; nf < NF; nf++) Ln[nf] = cL[lslot[nf] + s];
+        for (int nf = 0; nf < NF; nf++) {
+            if constexpr (NIB)
+                Lw[nf] = reinterpret_cast<const uint32_t *>(cL)[lslot[nf] + s];
+            else
+                Ln[nf] = cL[lslot[nf] + s];
+        }
+    };
+    auto build_b = [&]() {
+#pragma unroll
+        for (int nf = 0; nf < NF; nf++)
+            B[nf] = NIB ? onehot8_nib<BT>(Lw[nf], gg[nf]) : onehot8<BT>(Ln[nf], gg[nf]);
     };
     // MFMAs of the current step, then B and A of the next one.
     auto step = [&]() {
@@ -595,8 +658,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
 #pragma unroll
                 for (int nf = 0; nf < NF; nf++)
                     acc[rb][nf] = mma<BT>(Ac[rb][c], B[nf], acc[rb][nf]);
-#pragma unroll
-        for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(Ln[nf], gg[nf]);
+        build_b();
 #pragma unroll
         for (int rb = 0; rb < 4; rb++)
 #pragma unroll
@@ -641,8 +703,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     __syncthreads();
     stage(kb0 + 1, sA1, sL1);
     load_step(sA0, sL0, 0);
-#pragma unroll
-    for (int nf = 0; nf < NF; nf++) B[nf] = onehot8<BT>(Ln[nf], gg[nf]);
+    build_b();
 #pragma unroll
     for (int rb = 0; rb < 4; rb++)
 #pragma unroll
@@ -676,19 +737,33 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
             const uint2 *L2 = reinterpret_cast<const uint2 *>(rb < 2 ? sL0 : sL1);
+            const uint32_t *L1 = reinterpret_cast<const uint32_t *>(rb < 2 ? sL0 : sL1);
 #pragma unroll
-            for (int a = 0; a < 4; a++)
+            for (int a = 0; a < 4; a++) {
                 // rows rb*32 + 8a + 4*half + 0..3 of the panel: chunk
                 // (rb % 2) * 4 + a of its K block, bytes 8*half .. 8*half + 7
-                l4[rb][a] = L2[(slot0 + (rb % 2) * 4 + a) * 2 + half];
+                // (NIB: dword (rb % 2) * 4 + a, bits 16*half .. 16*half + 15)
+                if constexpr (NIB)
+                    l4[rb][a].x = L1[slot0 + (rb % 2) * 4 + a] >> (16 * half);
+                else
+                    l4[rb][a] = L2[(slot0 + (rb % 2) * 4 + a) * 2 + half];
+            }
         }
         float zs = 0.0f, zn = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                const uint32_t lab4[4] = {l4[rb][a].x & 0xFFFFu, l4[rb][a].x >> 16,
-                                          l4[rb][a].y & 0xFFFFu, l4[rb][a].y >> 16};
+                uint32_t lab4[4];
+                if constexpr (NIB) {
+#pragma unroll
+                    for (int b = 0; b < 4; b++) lab4[b] = (l4[rb][a].x >> (4 * b)) & 0xFu;
+                } else {
+                    lab4[0] = l4[rb][a].x & 0xFFFFu;
+                    lab4[1] = l4[rb][a].x >> 16;
+                    lab4[2] = l4[rb][a].y & 0xFFFFu;
+                    lab4[3] = l4[rb][a].y >> 16;
+                }
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
                     const float y = acc[rb][nf][4 * a + b];
@@ -698,7 +773,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
             }
         }
         zs += __shfl_xor(zs, 32);
-        const int64_t p = p_lo + slot0 / kLStride;
+        const int64_t p = p_lo + slot0 / (NIB ? 8 : kLStride);   // slot0 is in dwords for NIB
         if (cx) {
             zn += __shfl_xor(zn, 32);
             const uint32_t gc = g - (g > (uint32_t)Lg ? 1u : 0u);   // column within p
@@ -711,19 +786,19 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     }
 }
 
-template <int DT, int NF, int LQ>
+template <int DT, int NF, int LQ, bool NIB>
 __global__ __launch_bounds__(256) void k_mfma(
     const uint4 *__restrict__ tiles, int64_t comp_units, int64_t kb_total,
     const int32_t *__restrict__ tab, int64_t grid_real, int64_t nblocks,
-    const uint16_t *__restrict__ lab, int64_t n_pad, int cx, int32_t kcol,
-    const int32_t *__restrict__ Lp, int64_t P, float *__restrict__ z) {
+    const uint16_t *__restrict__ lab, const uint32_t *__restrict__ lab4, int64_t n_pad, int cx,
+    int32_t kcol, const int32_t *__restrict__ Lp, int64_t P, float *__restrict__ z) {
     const int64_t gpad = gridDim.x;
     const int64_t bid = blockIdx.x;
     const int64_t logical = (bid & 7) * (gpad >> 3) + (bid >> 3);
     if (logical >= grid_real) return;
     const int32_t Lg = cx ? *Lp : 0;
-    mfma_unit<DT, NF, LQ>(tiles, comp_units, kb_total, tab, logical / nblocks, logical % nblocks,
-                          lab, n_pad, cx != 0, kcol, Lg, P, z);
+    mfma_unit<DT, NF, LQ, NIB>(tiles, comp_units, kb_total, tab, logical / nblocks,
+                               logical % nblocks, lab, lab4, n_pad, cx != 0, kcol, Lg, P, z);
 }
 
 // Label-copy rounds for the permutations that COLS columns of k columns per
@@ -739,6 +814,20 @@ constexpr bool mfma_lds_fits(int dt, int nf, int lq) {
 int lq_bin(int cols, int32_t k) {
     const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 9, 256);
     for (int b : kLqBins)
+        if (need <= b) return b;
+    return -1;
+}
+// The same for labels packed four bits each (2 slots per permutation).
+// They pay off where the u16 labels a work-group copies per K block outweigh
+// its block of A (one or two columns per permutation and 512 columns: 257
+// permutations, 37 KB of labels beside 32 KB of A): at n = 100,000, k = 3 the
+// kernel took 33.0 ms against 34.0.  With fewer permutations per work-group
+// the extra one-hot work (four operations per dword instead of three) costs
+// more than the copy saves (n = 10,000, k = 5: 6.9 ms against 6.3).
+constexpr int kLqNibBins[3] = {1, 2, 3};
+int lq_bin_nib(int cols, int32_t k) {
+    const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 2, 256);
+    for (int b : kLqNibBins)
         if (need <= b) return b;
     return -1;
 }
@@ -758,8 +847,8 @@ __global__ __launch_bounds__(256) void k_mfma_worklist(const JobDesc *__restrict
     const UnitDesc u = units[logical];
     const JobDesc &j = jobs[u.job];
     const bool cx = j.cx != 0;
-    mfma_unit<2, NF, 10>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
-                         u.pgroup, j.lab_pm, j.n_pad_m, cx, cx ? j.k - 1 : j.k, cx ? *j.Lp : 0,
+    mfma_unit<2, NF, 10, false>((const uint4 *)j.tiles, j.comp_units, j.kb_total, j.tab, u.chunk,
+                         u.pgroup, j.lab_pm, nullptr, j.n_pad_m, cx, cx ? j.k - 1 : j.k, cx ? *j.Lp : 0,
                          j.R, j.z);
 }
 
@@ -870,27 +959,37 @@ int64_t prepass_blocks(int64_t n) {
     return b < comp_units ? b : comp_units;
 }
 
-template <int DT, int NF, int LQ>
+template <int DT, int NF, int LQ, bool NIB>
 void launch_mfma_t(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
                    int64_t grid_real, int64_t gpad, const uint16_t *lab, const int32_t *Lp,
-                   int64_t P, float *z, hipStream_t s) {
-    hipLaunchKernelGGL((k_mfma<DT, NF, LQ>), dim3((unsigned)gpad), dim3(256), 0, s, t, comp_units,
-                       pl.kb_total, tab, grid_real, pl.nblocks, lab, pl.n_pad, pl.cx ? 1 : 0,
-                       pl.kcol, Lp, P, z);
+                   int64_t P, float *z, hipStream_t s, const uint32_t *lab4 = nullptr) {
+    hipLaunchKernelGGL((k_mfma<DT, NF, LQ, NIB>), dim3((unsigned)gpad), dim3(256), 0, s, t,
+                       comp_units, pl.kb_total, tab, grid_real, pl.nblocks, lab, lab4, pl.n_pad,
+                       pl.cx ? 1 : 0, pl.kcol, Lp, P, z);
 }
 
 template <int DT, int NF>
 int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const int32_t *tab,
                    int64_t grid_real, int64_t gpad, const uint16_t *lab, const int32_t *Lp,
-                   int64_t P, float *z, hipStream_t s) {
+                   int64_t P, float *z, hipStream_t s, const uint32_t *lab4) {
+    if constexpr (DT != 3) {
+        // labels packed four bits each when the table was given (k <= 15)
+        if (lab4) {
+            switch (lq_bin_nib(4 * NF * 32, pl.kcol)) {
+            case 1: launch_mfma_t<DT, NF, 1, true>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s, lab4); return 0;
+            case 2: launch_mfma_t<DT, NF, 2, true>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s, lab4); return 0;
+            case 3: launch_mfma_t<DT, NF, 3, true>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s, lab4); return 0;
+            }
+        }
+    }
     switch (lq_bin(4 * NF * 32, pl.kcol)) {
-    case 2: launch_mfma_t<DT, NF, 2>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
-    case 4: launch_mfma_t<DT, NF, 4>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
-    case 5: launch_mfma_t<DT, NF, 5>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
-    case 7: launch_mfma_t<DT, NF, 7>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 2: launch_mfma_t<DT, NF, 2, false>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 4: launch_mfma_t<DT, NF, 4, false>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 5: launch_mfma_t<DT, NF, 5, false>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
+    case 7: launch_mfma_t<DT, NF, 7, false>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s); return 0;
     case 10:
         if constexpr (mfma_lds_fits(DT, NF, 10)) {
-            launch_mfma_t<DT, NF, 10>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s);
+            launch_mfma_t<DT, NF, 10, false>(pl, t, comp_units, tab, grid_real, gpad, lab, Lp, P, z, s);
             return 0;
         }
         return -1;
@@ -899,7 +998,8 @@ int launch_mfma_lq(const MfmaPlan &pl, const uint4 *t, int64_t comp_units, const
 }
 
 int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t *lab_pm,
-                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s, const int32_t *Lp) {
+                int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s, const int32_t *Lp,
+                const uint32_t *lab4) {
     (void)n;
     if (pl.ncols != 256 && pl.ncols != 512) return -1;
     if (k < 2 || (pl.kchunk & 1)) return -1;
@@ -913,8 +1013,10 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
 #define PSTAT_MFMA_CASE(DT_)                                                                      \
     if (pl.dtype == DT_) {                                                                        \
         if (pl.ncols == 512)                                                                      \
-            return launch_mfma_lq<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, s); \
-        return launch_mfma_lq<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, s);     \
+            return launch_mfma_lq<DT_, 4>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, \
+                                          s, lab4);                                               \
+        return launch_mfma_lq<DT_, 2>(pl, t, comp_units, tab, grid_real, gpad, lab_pm, Lp, P, z, s, \
+                                      lab4);                                                      \
     }
     PSTAT_MFMA_CASE(0)
     PSTAT_MFMA_CASE(1)
@@ -924,6 +1026,18 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
     return -1;
 }
 
+bool mfma_use_nibbles(const MfmaPlan &pl, int32_t k) {
+    return k <= 15 && pl.dtype != 3 && lq_bin(pl.ncols, pl.kcol) >= 7 &&
+           lq_bin_nib(pl.ncols, pl.kcol) > 0;
+}
+void launch_pack_nibbles(const uint16_t *lab, int64_t count, uint32_t *out, hipStream_t s) {
+    const int64_t words = count / 8;
+    if (words <= 0) return;
+    int64_t blocks = ceil_div(words, 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_pack_nibbles, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const uint4 *)lab, words, out);
+}
 void launch_mfma_worklist(const JobDesc *jobs, const UnitDesc *units, const int32_t *count,
                           int64_t max_units, hipStream_t s, int ncols) {
     const int64_t gpad = round_up(max_units > 0 ? max_units : 1, 8);

@@ -177,6 +177,10 @@ void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_ti
     L.mp = mfma_plan(n, P, k, mfma_dtype(path), kchunk_cols, ncols, dev_info().n_cu,
                      cx && own_tiles);
     L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
+    // fewer than 16 groups and many permutations per work-group: the MFMA
+    // kernel copies labels packed four bits each
+    if (mfma_use_nibbles(L.mp, k))
+        L.lab4 = (uint32_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad / 2);
     if (own_tiles) L.tiles = c.take(mfma_tile_bytes(n, mfma_dtype(path)));
     L.tab = (int32_t *)c.take(mfma_table_bytes(L.mp));
     const int32_t zc = L.mp.cx ? 2 * L.mp.kcol : k;   // z entries per grouping
@@ -246,8 +250,13 @@ int exec_sW(const SwLayout &L, const float *mat, int64_t n, const int32_t *g,
         launch_vnot(L.cx, L.lab, L.mp.n_pad, n, P, s);
         if ((rc = check_launch("complement sums"))) return rc;
     }
+    if (L.lab4) {
+        launch_pack_nibbles(L.lab, L.mp.n_pad * L.mp.P_pad, L.lab4, s);
+        if ((rc = check_launch("label packing"))) return rc;
+    }
     KernelTimer timer(s, timed);
-    if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s, L.mp.cx ? L.cx.L : nullptr))
+    if (launch_mfma(L.mp, tiles, n, L.lab, k, P, L.tab, L.z, s, L.mp.cx ? L.cx.L : nullptr,
+                    L.lab4))
         return fail(PSTAT_EINVAL, "no MFMA kernel for %d columns", L.mp.ncols);
     timer.stop(s);
     if ((rc = check_launch("mfma s_W"))) return rc;

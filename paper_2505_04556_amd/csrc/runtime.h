@@ -94,6 +94,7 @@ struct SwLayout {
     int path = 0;
     uint8_t *bad = nullptr;      // per-permutation "had a bad label" flags
     uint16_t *lab = nullptr;     // staged labels
+    uint32_t *lab4 = nullptr;    // MFMA, k <= 15: the same packed four bits each
     double *partial = nullptr;   // plain: [chunks][P_pad]
     void *tiles = nullptr;       // MFMA: pre-squared tiles (unless registered)
     int32_t *tab = nullptr;      // MFMA: work-item table

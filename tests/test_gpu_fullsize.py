@@ -9,7 +9,8 @@
   precision table -- and p identical for the forms that meet 1e-5.
 * n = 100,000 (40 GB matrix, k = 3, 999 permutations): 64-bit offsets; sampled
   permutations against the oracle fed by row blocks copied from the device,
-  F_obs against the oracle, and the p-value consistent with the returned s_W.
+  F_obs against the oracle, and the p-value consistent with the returned s_W;
+  the same varied matrix in the packed layout gives the same bits.
 * n = 229,376 in the packed layout (only the strict upper triangle): a size
   whose square layout would not fit beside the MFMA tiles; closed form.
 """
@@ -169,10 +170,12 @@ def test_n100000_sampled(ps):
     out = {}
     g = torch.from_numpy(rows).cuda()
     wd = torch.from_numpy(w).cuda()
+    square = {}
     for path in ("mfma_split_bf16", "plain_f32", "mfma_f16", "mfma_bf16"):
         res, sw, rech = whole_test(ps, D, cfg, path)
         got = np.concatenate([sw[:1], sw[1:][sample]])
         raw = ps.pstat_sW_k(D, g, k, wd).cpu().numpy()   # the form alone, sampled rows
+        square[path] = (res, sw, raw)
         out[path] = dict(max_rel_sW_sample=max_rel(got, acc),
                          max_rel_sW_form_only=max_rel(raw, acc),
                          rel_F_obs=abs(res[0] - F_obs) / abs(F_obs), rechecked=rech, p=res[1])
@@ -184,7 +187,34 @@ def test_n100000_sampled(ps):
         # p is the count of the returned s_W at or below the observed one
         # (ties within the tolerance included)
         assert res[1] == oracle.pvalue(sw[0], sw[1:])
-    record("n100000", dict(sample=sample, F_obs=F_obs, forms=out))
+    # The same matrix given as its packed strict upper triangle (varied
+    # values, element offsets past 2^32 in both layouts): every s_W, the
+    # whole test's and the sampled rows' alone, equal to the square
+    # layout's bit for bit -- and so within the tolerance of the row-block
+    # oracle above.
+    del D
+    ps.pstat_free_workspace()
+    torch.cuda.empty_cache()
+    Dp = sd.uniform_packed(n, cfg["matrix_seed"])
+    packed = {}
+    for path in ("mfma_split_bf16", "plain_f32"):
+        res, sw, _ = whole_test(ps, Dp, cfg, path)
+        raw = ps.pstat_sW_k(Dp, g, k, wd).cpu().numpy()
+        s_res, s_sw, s_raw = square[path]
+        packed[path] = dict(whole_test_identical=bool(np.array_equal(sw, s_sw)),
+                            sampled_rows_identical=bool(np.array_equal(raw, s_raw)),
+                            result_identical=bool(np.array_equal(res, s_res)),
+                            max_rel_sW_sample=max_rel(np.concatenate([sw[:1], sw[1:][sample]]),
+                                                      acc))
+        assert np.array_equal(sw, s_sw), path
+        assert np.array_equal(raw, s_raw), path
+        assert np.array_equal(res, s_res), path
+        assert max_rel(raw, acc) <= TOL[path]
+    ps.pstat_set_path("auto")
+    del Dp
+    ps.pstat_free_workspace()
+    torch.cuda.empty_cache()
+    record("n100000", dict(sample=sample, F_obs=F_obs, forms=out, packed_layout=packed))
 
 
 def test_n229376_packed_closed_form(ps):

@@ -133,10 +133,11 @@ def test_jobs_count_ties_like_the_oracle(ps, path):
 def test_serving_trace_matches_oracle_on_a_subset(ps):
     """The 64-request serving trace (n in 1k..20k, k in 2..12, 999 or 9,999
     permutations), served with all arrivals at once under an 8 GB budget on the
-    library's own choice of form; every request with n <= 2,000 (the ones the
-    FP64 oracle finishes in about a second) is checked against the oracle:
-    s_W of every permutation within 1e-5, F_obs within 1e-5, p identical.
-    Every request must complete."""
+    library's own choice of form.  Every request must complete, and each one's
+    s_W (all permutations) and result must equal pstat_permanova's on the
+    same form bit for bit; every request with n <= 2,000 (the ones the FP64
+    oracle finishes in about a second) is also checked against the oracle:
+    s_W of every permutation within 1e-5, F_obs within 1e-5, p identical."""
     import synth.device as sd
     from paper_2505_04556_amd.serve import GpuExecutor, Request, Server
     specs = synth.serving_requests(64, 4.0, 4000)
@@ -154,6 +155,18 @@ def test_serving_trace_matches_oracle_on_a_subset(ps):
     errors = {i: o.error for i, o in res["outcomes"].items() if o.error}
     assert not errors, errors
     assert res["stats"]["completed"] == 64
+    import torch
+    for r in reqs:
+        o = res["outcomes"][r.id]
+        ps.pstat_set_path(ps.resolve_path("auto", r.n, r.k))
+        D = r.make_matrix(torch.device("cuda"))
+        sw = torch.empty(r.n_perms + 1, dtype=torch.float64, device="cuda")
+        whole, _ = ps.pstat_permanova(D, torch.from_numpy(r.grouping).cuda(), r.k, r.n_perms,
+                                      r.seed, sW_all=sw)
+        assert np.array_equal(sw.cpu().numpy(), o.sW_all), r.id
+        assert list(whole.cpu().numpy()) == o.result, r.id
+        del D, sw
+    ps.pstat_set_path(ps.PSTAT_PATH_AUTO)
     checked = 0
     for t in specs:
         if t["n"] > 2000:
