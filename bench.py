@@ -64,7 +64,9 @@ def autotuned(ps, torch, D, cfg, paths):
     base = torch.from_numpy(synth.base_labels(cfg["sizes"])).cuda()
     perms = ps.pstat_permute(base, cfg["n_perms"], cfg["perm_seed"])
     w = torch.from_numpy(synth.inv_group_sizes(cfg["sizes"])).cuda()
-    entry = autotune.tune(D, perms, cfg["k"], w, paths=paths, reps=2, cache={}, save=False)
+    # ranked by whole-test time: what the timed steps run
+    entry = autotune.tune(D, perms, cfg["k"], w, paths=paths, reps=2, cache={}, save=False,
+                          whole=(base, cfg["n_perms"], cfg["perm_seed"]))
     del perms
     return entry
 
@@ -328,7 +330,7 @@ def recorded_traffic(kernel_src: str, summary: str):
 
 
 def serve_trace(budget_bytes: int, count: int, rate: float, arrival_seed: int,
-                budget_factor: float = 0.0):
+                budget_factor: float = 0.0, burst: bool = False):
     """One serving trace: Poisson arrivals (`rate` requests/s, arrival times from
     `arrival_seed`), n in {1k..20k}, k in 2..12 with Dirichlet sizes, 999 or
     9,999 permutations; continuous batching under an HBM budget (with
@@ -352,7 +354,7 @@ def serve_trace(budget_bytes: int, count: int, rate: float, arrival_seed: int,
     try:
         ex.warmup(reserve_bytes=budget_bytes)   # server start-up, before the first arrival
         srv = Server(ex, hbm_budget=budget_bytes, round_work=1.5e11, max_units=8192)
-        res = srv.run(reqs)
+        res = srv.run(reqs, realtime=not burst)
     finally:
         ex.close()
     res["budget_bytes"] = budget_bytes
@@ -360,19 +362,25 @@ def serve_trace(budget_bytes: int, count: int, rate: float, arrival_seed: int,
 
 
 def serve_leg(budget_bytes: int, count: int = 64, rate: float = 4.0, seeds: int = 1,
-              budget_factor: float = 0.0) -> dict:
+              budget_factor: float = 0.0, burst: bool = False) -> dict:
     """The serving trace at arrival seed 4000 (latency = result time - arrival
     time, nearest-rank quantiles); with seeds > 1 the same requests are replayed
     under arrival seeds 4001, ... and the latencies of all traces are pooled."""
     from paper_2505_04556_amd.serve import nearest_rank
-    res, forms = serve_trace(budget_bytes, count, rate, 4000, budget_factor)
+    res, forms = serve_trace(budget_bytes, count, rate, 4000, budget_factor, burst)
     budget_bytes = res["budget_bytes"]
     st = dict(res["stats"])
-    waited = sum(1 for o in res["outcomes"].values()
-                 if o.error is None and o.admitted - o.arrival > 0.05)
+    ok = [o for o in res["outcomes"].values() if o.error is None]
+    waits = sorted(o.admitted - o.arrival for o in ok)
+    waited = sum(1 for w in waits if w > 0.05)
     st.update(rounds=res["rounds"], peak_resident_GB=round(res["peak_bytes"] / 1e9, 3),
-              budget_GB=round(budget_bytes / 1e9, 3), requests=count, arrivals_per_s=rate,
-              admissions_delayed_50ms=waited, quantiles="nearest rank",
+              budget_GB=round(budget_bytes / 1e9, 3), requests=count,
+              arrivals=("all at t = 0" if burst else f"Poisson, {rate} per s"),
+              admissions_delayed_50ms=waited,
+              admissions_waited_1ms=sum(1 for w in waits if w > 0.001),
+              admission_wait_max_s=round(waits[-1], 4) if waits else None,
+              admission_wait_mean_s=round(sum(waits) / len(waits), 4) if waits else None,
+              quantiles="nearest rank",
               path="auto: work-list kernels of both forms in each round", jobs_by_form=forms)
     out = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
     if seeds > 1:
@@ -437,9 +445,13 @@ def main() -> int:
     ap.add_argument("--gemm-only", action="store_true",
                     help="measure only the vendor BF16 GEMM rate (for profiling it)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
-    ap.add_argument("--serve-tight-factor", type=float, default=1.25,
-                    help="budget of the second serving trace as a multiple of the largest "
-                         "request's footprint, where admission must queue (0 skips it)")
+    ap.add_argument("--plain-tuning", default="",
+                    help="TILE,LANES for the plain form instead of the tuned or default ones "
+                         "(e.g. 32,64: a lanes sweep)")
+    ap.add_argument("--serve-tight-factor", type=float, default=1.0,
+                    help="budget of a second serving run, all 64 requests arriving at once, as "
+                         "a multiple of the largest request's footprint: admission must queue "
+                         "(0 skips it)")
     ap.add_argument("--serve-seeds", type=int, default=1,
                     help="replay the serving trace under this many arrival seeds and pool "
                          "the latencies")
@@ -488,9 +500,13 @@ def main() -> int:
     if not args.no_tune:
         log("autotuning " + ", ".join(paths))
         entry = autotuned(ps, torch, D, cfg, tuple(paths))
-        tuned = {p: {kk: v[kk] for kk in ("tile", "batch", "kernel_ms", "hbm_frac") if kk in v}
+        tuned = {p: {kk: v[kk] for kk in ("tile", "batch", "kernel_ms", "whole_ms", "hbm_frac")
+                     if kk in v}
                  for p, v in entry["paths"].items()}
         log(f"  tuned: {tuned}")
+    if args.plain_tuning:
+        t_, l_ = (int(v) for v in args.plain_tuning.split(","))
+        tuned["plain_f32"] = {"tile": t_, "batch": l_}
     runs = {}
     for path in paths:
         log(f"timing {path}: {args.warmup} warm-up + {args.steps} steps")
@@ -568,8 +584,9 @@ def main() -> int:
         log(f"  serve: p50 {serve.get('p50_s')} s, p99 {serve.get('p99_s')} s, "
             f"{serve.get('G_pair_perms_per_s')} G pair-perms/s")
         if args.serve_tight_factor > 0:
-            log(f"serving trace under {args.serve_tight_factor:g} x the largest footprint")
-            tight = serve_leg(0, seeds=1, budget_factor=args.serve_tight_factor)
+            log(f"serving burst (all 64 at once) under {args.serve_tight_factor:g} x the "
+                f"largest footprint")
+            tight = serve_leg(0, seeds=1, budget_factor=args.serve_tight_factor, burst=True)
             serve["tight_budget"] = tight
             log(f"  serve (tight): p50 {tight.get('p50_s')} s, p99 {tight.get('p99_s')} s, "
                 f"delayed {tight.get('admissions_delayed_50ms')}")
