@@ -193,8 +193,8 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
                 int32_t k, int64_t P, int32_t *tab, float *z, hipStream_t s,
                 const int32_t *Lp = nullptr, const uint32_t *lab4 = nullptr);
 // Whether launch_mfma should be given the labels packed four bits each for
-// this plan (k <= 15, and enough permutations per work-group that their u16
-// labels would outweigh the matrix block it copies).
+// this plan (k <= 15; not the three-part split, whose A blocks leave the
+// u16 label buffers room).
 bool mfma_use_nibbles(const MfmaPlan &pl, int32_t k);
 // out (count / 8 dwords) = the u16 label table lab (count entries, a multiple
 // of 8, every real label below 15) packed four bits per label, padding as 15.

@@ -817,13 +817,11 @@ int lq_bin(int cols, int32_t k) {
         if (need <= b) return b;
     return -1;
 }
-// The same for labels packed four bits each (2 slots per permutation).
-// They pay off where the u16 labels a work-group copies per K block outweigh
-// its block of A (one or two columns per permutation and 512 columns: 257
-// permutations, 37 KB of labels beside 32 KB of A): at n = 100,000, k = 3 the
-// kernel took 33.0 ms against 34.0.  With fewer permutations per work-group
-// the extra one-hot work (four operations per dword instead of three) costs
-// more than the copy saves (n = 10,000, k = 5: 6.9 ms against 6.3).
+// The same for labels packed four bits each (2 slots per permutation).  The
+// copy shrinks by 4.5x (at k = 3, 512 columns: 257 permutations, 37 KB of u16
+// labels per K block beside 32 KB of A); the one-hot work grows from three
+// to four operations per dword.  Measured on one device: n = 100,000, k = 3
+// 30.9 ms against 34.0; n = 10,000, k = 5 6.15 ms against 6.25.
 constexpr int kLqNibBins[3] = {1, 2, 3};
 int lq_bin_nib(int cols, int32_t k) {
     const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 2, 256);
@@ -1027,8 +1025,7 @@ int launch_mfma(const MfmaPlan &pl, const void *tiles, int64_t n, const uint16_t
 }
 
 bool mfma_use_nibbles(const MfmaPlan &pl, int32_t k) {
-    return k <= 15 && pl.dtype != 3 && lq_bin(pl.ncols, pl.kcol) >= 7 &&
-           lq_bin_nib(pl.ncols, pl.kcol) > 0;
+    return k <= 15 && pl.dtype != 3 && lq_bin_nib(pl.ncols, pl.kcol) > 0;
 }
 void launch_pack_nibbles(const uint16_t *lab, int64_t count, uint32_t *out, hipStream_t s) {
     const int64_t words = count / 8;

@@ -177,8 +177,8 @@ void layout_sW(Carver &c, int64_t n, int64_t P, int32_t k, int path, bool own_ti
     L.mp = mfma_plan(n, P, k, mfma_dtype(path), kchunk_cols, ncols, dev_info().n_cu,
                      cx && own_tiles);
     L.lab = (uint16_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad * sizeof(uint16_t));
-    // fewer than 16 groups and many permutations per work-group: the MFMA
-    // kernel copies labels packed four bits each
+    // fewer than 16 groups: the MFMA kernel copies labels packed four bits
+    // each
     if (mfma_use_nibbles(L.mp, k))
         L.lab4 = (uint32_t *)c.take((size_t)L.mp.n_pad * L.mp.P_pad / 2);
     if (own_tiles) L.tiles = c.take(mfma_tile_bytes(n, mfma_dtype(path)));
