@@ -299,8 +299,6 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                         double sum = 0.0;
                         masked_add8(sum, rcol[q][cq + e], rl, d2);
                         acc[q] = __builtin_fma(sum, rw[q][cq + e], acc[q]);
-                        // one grouping's labels live at a time
-                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
             }
@@ -556,6 +554,8 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     __shared__ uint4 sA1[UNIT];
     __shared__ uint4 sL0[LSLOTS];
     __shared__ uint4 sL1[LSLOTS];
+    __shared__ uint4 sE0[NIB ? LSLOTS : 1];
+    __shared__ uint4 sE1[NIB ? LSLOTS : 1];
     const int64_t I = tab[3 * item], kb0 = tab[3 * item + 1], kb1 = tab[3 * item + 2];
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
@@ -699,6 +699,10 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     };
 
     stage(kb0, sA0, sL0);
+    if constexpr (NIB) {
+        stage_labels(2 * I, sE0);
+        stage_labels(2 * I + 1, sE1);
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     stage(kb0 + 1, sA1, sL1);
@@ -718,12 +722,19 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
 
     // Epilogue: keep the rows whose label equals the column's group.  The
     // panel's 128 rows are K blocks 2I and 2I + 1, so their labels are copied
-    // into the two label buffers in the same layout as in the loop.
-    __syncthreads();                 // every wave is done with the buffers
-    stage_labels(2 * I, sL0);
-    stage_labels(2 * I + 1, sL1);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // in the same layout as in the loop: with packed labels into two buffers
+    // of their own together with the first K block (their wait then falls on
+    // the prologue's, which is exposed anyway: 1% of the kernel at n =
+    // 100,000), with u16 labels (no room for two more buffers) into the
+    // loop's label buffers once the loop is done.
+    if constexpr (!NIB) {
+        __syncthreads();                 // every wave is done with the buffers
+        stage_labels(2 * I, sL0);
+        stage_labels(2 * I + 1, sL1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    const uint4 *E0 = NIB ? sE0 : sL0, *E1 = NIB ? sE1 : sL1;
 #pragma unroll
     for (int nf = 0; nf < NF; nf++) {
         // Derived again from the loop's two registers (an empty asm hides
@@ -736,8 +747,8 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
         uint2 l4[4][4];
 #pragma unroll
         for (int rb = 0; rb < 4; rb++) {
-            const uint2 *L2 = reinterpret_cast<const uint2 *>(rb < 2 ? sL0 : sL1);
-            const uint32_t *L1 = reinterpret_cast<const uint32_t *>(rb < 2 ? sL0 : sL1);
+            const uint2 *L2 = reinterpret_cast<const uint2 *>(rb < 2 ? E0 : E1);
+            const uint32_t *L1 = reinterpret_cast<const uint32_t *>(rb < 2 ? E0 : E1);
 #pragma unroll
             for (int a = 0; a < 4; a++) {
                 // rows rb*32 + 8a + 4*half + 0..3 of the panel: chunk
@@ -805,11 +816,13 @@ __global__ __launch_bounds__(256) void k_mfma(
 // grouping can touch ((COLS - 1) / k + 2, 9 slots each, 256 per round),
 // rounded up to the instantiated counts.
 constexpr int kLqBins[5] = {2, 4, 5, 7, 10};
-// Static LDS of k_mfma<DT, NF, LQ>: two buffers of A (one 16 KB block per
-// component) and two of labels; gfx950 gives a work-group 160 KB.
-constexpr bool mfma_lds_fits(int dt, int nf, int lq) {
+// Static LDS of k_mfma<DT, NF, LQ, NIB>: two buffers of A (one 16 KB block
+// per component) and two of labels, with packed labels two more for the
+// epilogue's; gfx950 gives a work-group 160 KB.
+constexpr bool mfma_lds_fits(int dt, int nf, int lq, bool nib = false) {
     (void)nf;
-    return 2 * (dt == 3 ? 3 : dt == 2 ? 2 : 1) * kUnitU4 * 16 + 2 * lq * 256 * 16 <= 160 * 1024;
+    return 2 * (dt == 3 ? 3 : dt == 2 ? 2 : 1) * kUnitU4 * 16 + (nib ? 4 : 2) * lq * 256 * 16 <=
+           160 * 1024;
 }
 int lq_bin(int cols, int32_t k) {
     const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 9, 256);
@@ -823,6 +836,8 @@ int lq_bin(int cols, int32_t k) {
 // to four operations per dword.  Measured on one device: n = 100,000, k = 3
 // 30.9 ms against 34.0; n = 10,000, k = 5 6.15 ms against 6.25.
 constexpr int kLqNibBins[3] = {1, 2, 3};
+static_assert(mfma_lds_fits(2, 4, 3, true) && mfma_lds_fits(0, 4, 3, true),
+              "packed-label kernels fit in LDS");
 int lq_bin_nib(int cols, int32_t k) {
     const int64_t need = ceil_div(((int64_t)(cols - 1) / k + 2) * 2, 256);
     for (int b : kLqNibBins)
