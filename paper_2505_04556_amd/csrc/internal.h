@@ -19,6 +19,19 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // Number of tiles of an upper-triangular tiling with nt tiles per side.
 inline int64_t tri_count(int64_t nt) { return nt * (nt + 1) / 2; }
 
+// Upper-triangle tile t (row-major over tile rows I, J = I .. nt-1) -> (I, J).
+__device__ inline void tri_decode(int64_t t, int64_t nt, int64_t &I, int64_t &J) {
+    const double b = 2.0 * (double)nt + 1.0;
+    int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > nt - 1) r = nt - 1;
+    auto off = [nt](int64_t x) { return x * nt - x * (x - 1) / 2; };
+    while (r > 0 && off(r) > t) --r;
+    while (r + 1 < nt && off(r + 1) <= t) ++r;
+    I = r;
+    J = r + (t - off(r));
+}
+
 // Layouts of D in device memory: the row-major n x n square (packed == 0),
 // or only its strict upper triangle, row after row (packed != 0: row i holds
 // columns i + 1 .. n - 1 and starts at i (2n - i - 1) / 2; n (n - 1) / 2
