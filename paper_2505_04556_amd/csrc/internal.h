@@ -270,12 +270,14 @@ void launch_pack_result(const double *sW_all, const double *sT, int64_t n, int32
                         const uint32_t *counts, const double *p, double *result, hipStream_t s);
 
 // ---- permutation generator (k_permute.hip) -----------------------------------
+// lds_limit: LDS bytes a work-group may use; n_cu: compute units (the lanes
+// per permutation depend on whether every permutation runs at once).
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
-                   int32_t *out, size_t lds_limit, hipStream_t s);
+                   int32_t *out, size_t lds_limit, int n_cu, hipStream_t s);
 // The same permutations written as u16 rows of `stride` entries (row p at
 // out + p * stride), padded with kPadLabel: the MFMA forms' staged layout.
 // Returns nonzero (nothing launched) when no LDS-resident form fits.
 int launch_permute_u16(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
-                       uint16_t *out, int64_t stride, size_t lds_limit, hipStream_t s);
+                       uint16_t *out, int64_t stride, size_t lds_limit, int n_cu, hipStream_t s);
 
 } // namespace pstat

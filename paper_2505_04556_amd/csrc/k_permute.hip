@@ -114,9 +114,10 @@ __device__ inline uint64_t group_mask(int gbase) {
 
 // Label storage of the batched shuffle.  WideStore keeps one label per
 // 8- or 16-bit entry; each lane with nothing to swap swaps a private dummy
-// slot, so a batch's writes never race.  NibbleStore packs labels below 16
+// slot, so a batch's writes never race.  PackedStore packs labels below 16
 // eight to a 32-bit word (n = 10,000 takes 5,000 bytes, so twice as many
-// arrays share a CU's LDS) and writes by xor: a swap of values u and v adds
+// arrays share a CU's LDS), or labels below 4 sixteen to a word, and writes
+// by xor: a swap of values u and v adds
 // u ^ v into both positions with an LDS atomic xor, so swaps of different
 // positions in one word commute, and a lane with nothing to swap adds zero.
 template <typename E>
@@ -184,14 +185,21 @@ struct WideStore {
     }
 };
 
-struct NibbleStore {
-    static constexpr size_t row_bytes(int64_t n) { return (size_t)((n + 7) / 8) * 4; }
+template <int BITS>
+struct PackedStore {
+    static constexpr int PER = 32 / BITS;               // labels per word
+    static constexpr uint32_t MASK = (1u << BITS) - 1;
+    static constexpr size_t row_bytes(int64_t n) { return (size_t)((n + PER - 1) / PER) * 4; }
     static constexpr size_t spare_bytes() { return 0; }
-    uint32_t *w;   // this lane's array, eight labels per word
-    __device__ NibbleStore(unsigned char *smem, int64_t n, int slot, int, int)
-        : w(reinterpret_cast<uint32_t *>(smem) + (int64_t)slot * ((n + 7) / 8)) {}
-    __device__ uint32_t get(uint32_t i) const { return (w[i >> 3] >> (4 * (i & 7))) & 15u; }
-    __device__ void flip(uint32_t i, uint32_t d) const { atomicXor(&w[i >> 3], d << (4 * (i & 7))); }
+    uint32_t *w;   // this lane's array, PER labels per word
+    __device__ PackedStore(unsigned char *smem, int64_t n, int slot, int, int)
+        : w(reinterpret_cast<uint32_t *>(smem) + (int64_t)slot * ((n + PER - 1) / PER)) {}
+    __device__ uint32_t get(uint32_t i) const {
+        return (w[i / PER] >> (BITS * (i % PER))) & MASK;
+    }
+    __device__ void flip(uint32_t i, uint32_t d) const {
+        atomicXor(&w[i / PER], d << (BITS * (i % PER)));
+    }
     __device__ void swap(int32_t i, int32_t j) const {
         const uint32_t d = get((uint32_t)i) ^ get((uint32_t)j);
         flip((uint32_t)i, d);
@@ -200,73 +208,79 @@ struct NibbleStore {
     template <typename F>
     __device__ void swap_all(bool now, int32_t i, int32_t j, F &&between) const {
         const uint32_t ia = now ? (uint32_t)i : 0u, ib = now ? (uint32_t)j : 0u;
-        const uint32_t wa = w[ia >> 3], wb = w[ib >> 3];
+        const uint32_t wa = w[ia / PER], wb = w[ib / PER];
         between();
-        const uint32_t sa = 4 * (ia & 7), sb = 4 * (ib & 7);
-        const uint32_t d = ((wa >> sa) ^ (wb >> sb)) & 15u;   // 0 for a lane with nothing to swap
-        atomicXor(&w[ia >> 3], d << sa);
-        atomicXor(&w[ib >> 3], d << sb);
+        const uint32_t sa = BITS * (ia % PER), sb = BITS * (ib % PER);
+        const uint32_t d = ((wa >> sa) ^ (wb >> sb)) & MASK;   // 0 for a lane with nothing to swap
+        atomicXor(&w[ia / PER], d << sa);
+        atomicXor(&w[ib / PER], d << sb);
     }
     __device__ static void fill(unsigned char *smem, const int32_t *base, int64_t n, int live,
                                 int vec, int tid, int nthr) {
         uint32_t *arr = reinterpret_cast<uint32_t *>(smem);
-        const int64_t nw = (n + 7) / 8;
+        const int64_t nw = (n + PER - 1) / PER;
         for (int64_t v = tid; v < nw; v += nthr) {
             uint32_t word = 0;
-            if (vec && 8 * v + 8 <= n) {
-                const int4 b0 = reinterpret_cast<const int4 *>(base)[2 * v];
-                const int4 b1 = reinterpret_cast<const int4 *>(base)[2 * v + 1];
-                word = (uint32_t)b0.x | (uint32_t)b0.y << 4 | (uint32_t)b0.z << 8 |
-                       (uint32_t)b0.w << 12 | (uint32_t)b1.x << 16 | (uint32_t)b1.y << 20 |
-                       (uint32_t)b1.z << 24 | (uint32_t)b1.w << 28;
+            if (vec && PER * v + PER <= n) {
+#pragma unroll
+                for (int r = 0; r < PER / 4; r++) {
+                    const int4 b = reinterpret_cast<const int4 *>(base)[(PER / 4) * v + r];
+                    word |= ((uint32_t)b.x << (BITS * (4 * r))) |
+                            ((uint32_t)b.y << (BITS * (4 * r + 1))) |
+                            ((uint32_t)b.z << (BITS * (4 * r + 2))) |
+                            ((uint32_t)b.w << (BITS * (4 * r + 3)));
+                }
             } else {
-                for (int e = 0; e < 8; e++)
-                    if (8 * v + e < n) word |= (uint32_t)base[8 * v + e] << (4 * e);
+                for (int e = 0; e < PER; e++)
+                    if (PER * v + e < n) word |= (uint32_t)base[PER * v + e] << (BITS * e);
             }
             for (int q = 0; q < live; q++) arr[(int64_t)q * nw + v] = word;
         }
     }
-    // Copy out into rows of `stride` entries: int32 rows (two 16-byte stores
-    // per word when `vec`), or u16 rows (one 16-byte store per word when
-    // `vec`) padded with kPadLabel up to the stride.
+    // Copy out into rows of `stride` entries: int32 rows (PER / 4 16-byte
+    // stores per word when `vec`), or u16 rows (PER / 8 16-byte stores per
+    // word when `vec`) padded with kPadLabel up to the stride.
     template <typename O>
     __device__ static void drain(const unsigned char *smem, O *out, int64_t stride, int64_t p0,
                                  int64_t n, int live, int vec, int tid, int nthr) {
         const uint32_t *arr = reinterpret_cast<const uint32_t *>(smem);
-        const int64_t nw = (n + 7) / 8;
+        const int64_t nw = (n + PER - 1) / PER;
         for (int q = 0; q < live; q++) {
             const uint32_t *src = arr + (int64_t)q * nw;
             O *dst = out + (p0 + q) * stride;
             for (int64_t v = tid; v < nw; v += nthr) {
                 const uint32_t word = src[v];
-                const int64_t i0 = 8 * v;
-                if (vec && i0 + 8 <= n) {
+                const int64_t i0 = PER * v;
+                auto lab = [&](int e) { return (word >> (BITS * e)) & MASK; };
+                if (vec && i0 + PER <= n) {
                     if constexpr (sizeof(O) == 4) {
-                        *reinterpret_cast<int4 *>(dst + i0) =
-                            make_int4(word & 15u, (word >> 4) & 15u, (word >> 8) & 15u,
-                                      (word >> 12) & 15u);
-                        *reinterpret_cast<int4 *>(dst + i0 + 4) =
-                            make_int4((word >> 16) & 15u, (word >> 20) & 15u, (word >> 24) & 15u,
-                                      word >> 28);
+#pragma unroll
+                        for (int r = 0; r < PER / 4; r++)
+                            *reinterpret_cast<int4 *>(dst + i0 + 4 * r) =
+                                make_int4(lab(4 * r), lab(4 * r + 1), lab(4 * r + 2),
+                                          lab(4 * r + 3));
                     } else {
-                        // u16 pairs: nibbles 2e and 2e + 1 into one dword
-                        const uint32_t lo = word & 0x0F0F0F0Fu, hi = (word >> 4) & 0x0F0F0F0Fu;
-                        // bytes of lo: labels 0, 2, 4, 6; of hi: 1, 3, 5, 7
-                        const uint32_t d0 = (lo & 0xFFu) | ((hi & 0xFFu) << 16);
-                        const uint32_t d1 = ((lo >> 8) & 0xFFu) | (((hi >> 8) & 0xFFu) << 16);
-                        const uint32_t d2 = ((lo >> 16) & 0xFFu) | (((hi >> 16) & 0xFFu) << 16);
-                        const uint32_t d3 = (lo >> 24) | ((hi >> 24) << 16);
-                        *reinterpret_cast<uint4 *>(dst + i0) = make_uint4(d0, d1, d2, d3);
+#pragma unroll
+                        for (int r = 0; r < PER / 8; r++)
+                            *reinterpret_cast<uint4 *>(dst + i0 + 8 * r) =
+                                make_uint4(lab(8 * r) | lab(8 * r + 1) << 16,
+                                           lab(8 * r + 2) | lab(8 * r + 3) << 16,
+                                           lab(8 * r + 4) | lab(8 * r + 5) << 16,
+                                           lab(8 * r + 6) | lab(8 * r + 7) << 16);
                     }
                 } else {
-                    for (int e = 0; e < 8; e++)
-                        if (i0 + e < n) dst[i0 + e] = (O)((word >> (4 * e)) & 15u);
+                    for (int e = 0; e < PER; e++)
+                        if (i0 + e < n) dst[i0 + e] = (O)lab(e);
                 }
             }
             for (int64_t i = n + tid; i < stride; i += nthr) dst[i] = (O)kPadLabel;
         }
     }
 };
+// labels below 16, eight to a word; labels below 4, sixteen to a word (n =
+// 100,000 takes 25,000 bytes: six arrays share a CU's LDS instead of three)
+using NibbleStore = PackedStore<4>;
+using CrumbStore = PackedStore<2>;
 
 // Batched shuffle: B lanes per permutation, 64 / B permutations per wave,
 // blockDim.x / 64 waves per work-group, arrays in dynamic LDS as S stores them;
@@ -522,7 +536,7 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
 // small enough share a CU.
 template <typename S, typename O>
 int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *out,
-                 int64_t ostride, size_t lds_limit, hipStream_t s) {
+                 int64_t ostride, size_t lds_limit, int n_cu, hipStream_t s) {
     const size_t row = S::row_bytes(n);
     const size_t spare = S::spare_bytes();       // the per-thread dummy slots
     if (lds_limit <= spare) return 1;
@@ -532,7 +546,15 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
     if (fit > P) fit = P;
     int B, pw;
     int64_t waves;
-    if (fit >= 4) {
+    // Arrays a CU holds with one per wave (64 lanes each): work-groups of w
+    // waves, as many as its LDS takes.  When that runs every permutation at
+    // once, each gets a whole wave (the shortest chain of batches); with
+    // more permutations than that, 16 lanes each and several per wave.
+    const int64_t per_cu = fit;
+    int64_t w64 = per_cu < 4 ? per_cu : 4;
+    for (int64_t w = w64; w >= 1; --w)
+        if ((per_cu / w) * w > (per_cu / w64) * w64) w64 = w;
+    if (fit >= 4 && P > (int64_t)(n_cu > 0 ? n_cu : 256) * per_cu) {
         B = 16;
         pw = (int)ceil_div(fit, 4);
         if (pw == 3) pw = 2;                     // 1, 2 or 4 arrays per wave
@@ -541,7 +563,7 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
     } else {
         B = 64;
         pw = 1;
-        waves = fit;
+        waves = w64;
     }
     const int64_t ppg = waves * pw;
     const size_t bytes = (size_t)ppg * row + spare;
@@ -567,15 +589,17 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
 } // namespace
 
 int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
-                   int32_t *out, size_t lds_limit, hipStream_t s) {
+                   int32_t *out, size_t lds_limit, int n_cu, hipStream_t s) {
     if (P <= 0 || n <= 0) return 0;
-    if (max_label < 16 && launch_batch<NibbleStore>(base, n, P, seed, out, n, lds_limit, s) == 0)
+    if (max_label < 4 && launch_batch<CrumbStore>(base, n, P, seed, out, n, lds_limit, n_cu, s) == 0)
+        return 0;
+    if (max_label < 16 && launch_batch<NibbleStore>(base, n, P, seed, out, n, lds_limit, n_cu, s) == 0)
         return 0;
     if (max_label < 256 &&
-        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, n, lds_limit, s) == 0)
+        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, n, lds_limit, n_cu, s) == 0)
         return 0;
     if (max_label < 65536 &&
-        launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, n, lds_limit, s) == 0)
+        launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, n, lds_limit, n_cu, s) == 0)
         return 0;
     if (max_label < 256 && launch_lds<uint8_t>(base, n, P, seed, out, lds_limit, s) == 0) return 0;
     if (max_label < 65536 && launch_lds<uint16_t>(base, n, P, seed, out, lds_limit, s) == 0)
@@ -586,16 +610,19 @@ int launch_permute(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int
 }
 
 int launch_permute_u16(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t max_label,
-                       uint16_t *out, int64_t stride, size_t lds_limit, hipStream_t s) {
+                       uint16_t *out, int64_t stride, size_t lds_limit, int n_cu, hipStream_t s) {
     if (P <= 0 || n <= 0) return 0;
     if (stride < n || max_label >= 65535) return 1;
+    if (max_label < 4 &&
+        launch_batch<CrumbStore>(base, n, P, seed, out, stride, lds_limit, n_cu, s) == 0)
+        return 0;
     if (max_label < 16 &&
-        launch_batch<NibbleStore>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+        launch_batch<NibbleStore>(base, n, P, seed, out, stride, lds_limit, n_cu, s) == 0)
         return 0;
     if (max_label < 256 &&
-        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+        launch_batch<WideStore<uint8_t>>(base, n, P, seed, out, stride, lds_limit, n_cu, s) == 0)
         return 0;
-    if (launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, stride, lds_limit, s) == 0)
+    if (launch_batch<WideStore<uint16_t>>(base, n, P, seed, out, stride, lds_limit, n_cu, s) == 0)
         return 0;
     return 1;
 }

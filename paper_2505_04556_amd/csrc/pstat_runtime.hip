@@ -344,7 +344,8 @@ int prepare_test(const TestHead &h, int64_t n, const int32_t *grouping, int32_t 
                  int64_t n_perms, uint64_t seed, int32_t max_label) {
     hipStream_t s = tls.stream;
     HIP_TRY(hipMemcpyAsync(h.allg, grouping, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    launch_permute(grouping, n, n_perms, seed, max_label, h.allg + n, dev_info().lds_limit, s);
+    launch_permute(grouping, n, n_perms, seed, max_label, h.allg + n, dev_info().lds_limit,
+                   dev_info().n_cu, s);
     int rc = check_launch("permute");
     if (rc) return rc;
     launch_group_weights(grouping, n, k, h.counts, h.w, s);
@@ -654,7 +655,7 @@ int pstat_permute(const int32_t *base, int64_t n, int64_t n_perms, uint64_t seed
     int32_t max_label = -1;
     if ((rc = scan_labels_sync(base, n, kMaxGroups, &max_label))) return rc;
     launch_permute(base, n, n_perms, seed, max_label, groupings, dev_info().lds_limit,
-                   tls.stream);
+                   dev_info().n_cu, tls.stream);
     return check_launch("permute");
 }
 
@@ -703,7 +704,7 @@ int pstat_permanova(const float *mat, int64_t n, const int32_t *grouping, int32_
         const int64_t np = L.mp.n_pad;
         launch_fill_u8(L.bad, R, 0, s);
         staged = launch_permute_u16(grouping, n, n_perms, seed, max_label, L.lab + np, np,
-                                    dev_info().lds_limit, s) == 0;
+                                    dev_info().lds_limit, dev_info().n_cu, s) == 0;
         if (staged) {
             if ((rc = check_launch("permute"))) return rc;
             launch_stage_labels_pm(grouping, n, 1, np, 1, k, L.lab, L.bad, tls.flags, s);

@@ -58,6 +58,11 @@ def test_device_generators_match_host(ps):
     # in-order replay of a batch is exercised
     (10_000, 4, 400, 13), (12_000, 4, 200, 13), (60_000, 6, 24, 13),
     (10_000, 40, 400, 13), (60_000, 100, 24, 13), (10_003, 15, 256, 13),
+    # labels below 4 packed two bits to an entry: a whole wave per
+    # permutation while every permutation fits on the device at once, 16
+    # lanes each beyond that; nibbles and bytes with 16 lanes each
+    (100_000, 2, 40, 13), (60_000, 3, 24, 13), (10_000, 3, 400, 13),
+    (5_000, 3, 5_000, 13), (5_000, 9, 5_000, 13), (5_000, 100, 5_000, 13),
 ])
 def test_permute_bit_exact(ps, n, maxlab, P, seed):
     import torch
