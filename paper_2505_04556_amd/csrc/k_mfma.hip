@@ -16,7 +16,8 @@
 // computes Y = U_panel * G over a K range for 256 or 512 columns (p, g) of G at
 // a time with v_mfma_f32_32x32x16_{bf16,f16} (FP32 accumulation), staging the
 // K blocks of U in LDS and building the one-hot B fragments in registers from
-// u16 labels, and in its epilogue keeps
+// the staged labels (u16, or four bits each for k <= 15), and in its epilogue
+// keeps
 // for each column (p, g) only the rows i whose label is g:
 //     z[item][p][g] = sum_{i in panel, g_p(i) = g} Y[i][(p, g)].
 // Each (panel, K chunk) work item writes its own z; they are summed in FP64 and
