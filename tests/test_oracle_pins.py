@@ -455,3 +455,59 @@ def test_permutation_golden_fixture():
     base = np.array(rows[0], dtype=np.int32)
     got = oracle.permute(base, len(rows) - 1, seed=3000)
     assert got.tolist() == rows[1:]
+
+
+# --- P12: generated tiny problems against the defining sum in rationals ------
+# Hypothesis draws the inputs (derandomized, so every run checks the same
+# examples): arbitrary non-negative FP32 distances (zeros, subnormals and
+# large values included), any labels in range, any positive FP64 weights.
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+_f32 = st.floats(min_value=0.0, max_value=2.0 ** 60, allow_nan=False, allow_infinity=False,
+                 width=32)
+
+
+@st.composite
+def _tiny_problem(draw):
+    n = draw(st.integers(min_value=2, max_value=9))
+    k = draw(st.integers(min_value=1, max_value=4))
+    vals = draw(st.lists(_f32, min_size=n * n, max_size=n * n))
+    D = np.array(vals, dtype=np.float32).reshape(n, n)
+    P = draw(st.integers(min_value=1, max_value=3))
+    g = np.array(draw(st.lists(st.integers(0, k - 1), min_size=P * n, max_size=P * n)),
+                 dtype=np.int32).reshape(P, n)
+    w = np.array(draw(st.lists(st.floats(min_value=1e-3, max_value=1e3), min_size=k,
+                               max_size=k)), dtype=np.float64)
+    return D, g, w
+
+
+@settings(max_examples=300, derandomize=True, deadline=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(_tiny_problem())
+def test_generated_problems_match_exact_sum(prob):
+    D, g, w = prob
+    n = D.shape[0]
+    s = oracle.sW(D, g, w)
+    for p in range(g.shape[0]):
+        exact = Fraction(0)
+        scale = Fraction(0)   # the same sum of absolute terms, for the bound
+        for i in range(n):
+            for j in range(i + 1, n):
+                if g[p, i] == g[p, j]:
+                    term = Fraction(float(D[i, j])) ** 2 * Fraction(float(w[g[p, i]]))
+                    exact += term
+                    scale += abs(term)
+        # FP64 with compensated sums: a few units of rounding of the terms'
+        # magnitude (each product d*d*w is rounded once or twice)
+        assert abs(Fraction(float(s[p])) - exact) <= scale * Fraction(4, 2 ** 52)
+
+
+@settings(max_examples=200, derandomize=True, deadline=None)
+@given(st.lists(st.floats(min_value=-1e6, max_value=1e6, allow_nan=False), min_size=1,
+                max_size=40),
+       st.floats(min_value=-1e6, max_value=1e6, allow_nan=False))
+def test_generated_pvalues_match_direct_count(perm, obs):
+    perm = np.array(perm, dtype=np.float64)
+    # p = (1 + #{s_W_perm <= s_W_obs}) / (1 + P), counted here one by one
+    count = sum(1 for v in perm if v <= obs)
+    assert oracle.pvalue(obs, perm, rtol=0.0) == (1 + count) / (1 + len(perm))
