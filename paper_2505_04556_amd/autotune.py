@@ -37,7 +37,7 @@ import torch
 import paper_2505_04556_amd as ps
 
 PLAIN_SPACE = [(t, b) for t in (32, 64) for b in (64, 128, 256)]
-MFMA_SPACE = [(kc, nc) for kc in (512, 1024, 2048, 4096) for nc in (256, 512)]
+MFMA_SPACE = [(kc, nc) for kc in (512, 1024, 1536, 2048, 4096) for nc in (256, 512)]
 ACCURATE = ("plain_f32", "mfma_split_bf16", "mfma_split3_bf16")
 PEAK_HBM_BYTES_S = 8e12   # MI355X HBM3E
 ALL_PATHS = ("plain_f32", "mfma_split_bf16", "mfma_bf16", "mfma_f16")
