@@ -13,6 +13,8 @@
   the same varied matrix in the packed layout gives the same bits.
 * n = 229,376 in the packed layout (only the strict upper triangle): a size
   whose square layout would not fit beside the MFMA tiles; closed form.
+* n = 1,000 with 199,999 permutations: every s_W and the p-value against the
+  oracle on both forms.
 """
 import json
 import os
@@ -253,3 +255,34 @@ def test_n229376_packed_closed_form(ps):
     assert np.all(sw == 0.125 * (n - k))
     assert res[0] == 1.0 and res[1] == 1.0
     assert res[3] == 0.125 * (n - 1)
+
+
+def test_many_permutations(ps):
+    """n = 1,000 (k = 4, the 100/200/300/400 workload) with 199,999
+    permutations -- the paper's range reaches 10^6 -- on both forms: every
+    s_W against the oracle, p identical (hundreds of column blocks, label
+    tables of 0.4 GB, several FP64 recheck passes)."""
+    import torch
+    cfg = synth.config(0)
+    n, sizes, k = cfg["n"], cfg["sizes"], cfg["k"]
+    P, seed = 199_999, 77
+    D = synth.uniform_matrix(n, cfg["matrix_seed"])
+    ref = oracle.permanova(D, synth.base_labels(sizes), P, seed)
+    Dd = torch.from_numpy(D).cuda()
+    base = torch.from_numpy(synth.base_labels(sizes)).cuda()
+    out = {}
+    for path in ("plain_f32", "mfma_split_bf16"):
+        ps.pstat_set_path(path)
+        sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        res, rech = ps.pstat_permanova(Dd, base, k, P, seed, sW_all=sw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r, s = res.cpu().numpy(), sw.cpu().numpy()
+        err = max_rel(s[1:], ref["sW_perm"])
+        out[path] = dict(p=float(r[1]), rechecked=rech, max_rel_err=err, seconds=round(dt, 4))
+        assert err <= TOL[path], (path, err)
+        assert s[0] == r[2]
+        assert r[1] == ref["p"], (path, r[1], ref["p"])
+    ps.pstat_set_path("auto")
+    record("n1000_P199999", dict(oracle_p=ref["p"], forms=out))
