@@ -596,6 +596,36 @@ def test_permanova_constant_matrix_ties(ps, path, sizes, c):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-9
 
 
+# (3) Near ties in bulk: entries of 0.5 and its FP32 neighbours, so every
+# permutation's s_W lies within a few units of 1e-8 (relative) of every
+# other -- about the MFMA forms' own error -- and most of the shuffles fall
+# inside the recheck band: many FP64 recheck passes, and every one of them
+# must land on the oracle's side of the edge.
+@pytest.mark.parametrize("path", ["mfma_split_bf16", "mfma_bf16", "plain_f32"])
+def test_permanova_bulk_near_ties(ps, path):
+    import torch
+    n, sizes, P, seed = 500, [150, 150, 200], 999, 21
+    rng = np.random.default_rng(8)
+    up = np.nextafter(np.float32(0.5), np.float32(1.0))
+    dn = np.nextafter(np.float32(0.5), np.float32(0.0))
+    choice = rng.integers(0, 3, size=(n, n))
+    D = np.where(choice == 0, np.float32(0.5), np.where(choice == 1, up, dn)).astype(np.float32)
+    D = np.triu(D, 1)
+    D = D + D.T
+    base = synth.base_labels(sizes)
+    ref = oracle.permanova(D, base, P, seed)
+    spread = (ref["sW_perm"].max() - ref["sW_perm"].min()) / ref["sW_obs"]
+    assert spread < 1e-6
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, len(sizes), P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    assert res[1] == ref["p"], (path, res[1], ref["p"], rechecked, spread)
+    assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
+
+
 # The library keeps its state (stream, workspace, flags, form) per host
 # thread: two threads running whole tests on their own streams at once get
 # exactly what each gets alone.
