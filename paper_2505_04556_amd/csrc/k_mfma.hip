@@ -629,7 +629,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // Scheduling barriers pin this order (left to itself the compiler reads
     // each A fragment just before its MFMAs, exposing the LDS latency).
     uint4 Ac[4][NC], An[4][NC];
-    uint4 Ln[NF], B[NF];
+    uint4 Ln[NF], BX[2][NF];   // one-hot fragments of alternate K steps
     uint32_t Lw[NF];
     auto load_step = [&](const uint4 *cA, const uint4 *cL, int s) {
 #pragma unroll
@@ -644,34 +644,68 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                 Ln[nf] = cL[lslot[nf] + s];
         }
     };
-    auto build_b = [&]() {
+    auto build_b = [&](uint4 *B) {
 #pragma unroll
         for (int nf = 0; nf < NF; nf++)
             B[nf] = NIB ? onehot8_nib<BT>(Lw[nf], gg[nf]) : onehot8<BT>(Ln[nf], gg[nf]);
     };
-    // MFMAs of the current step, then B and A of the next one.
-    auto step = [&]() {
+    // One dword (two 16-bit one-hot values) of the next step's fragment nf.
+    auto onehot_piece = [&](uint4 *Bn, int nf, int q, uint32_t y) {
+        const uint32_t one1 = 0x00010001u;
+        const uint32_t onev = One<BT>::v | (One<BT>::v << 16);
+        uint32_t x;
+        if constexpr (NIB) {
+            const uint32_t sel = (uint32_t)q | 0x0C00u | ((uint32_t)q << 16) | 0x0C000000u;
+            x = __builtin_amdgcn_perm(0u, y, sel) & 0x00F0000Fu;
+        } else {
+            const uint32_t in[4] = {Ln[nf].x, Ln[nf].y, Ln[nf].z, Ln[nf].w};
+            x = in[q] ^ gg[nf];
+        }
+        uint32_t t, o;
+        asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(t) : "v"(one1), "v"(x));
+        asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(o) : "v"(t), "v"(onev));
+        if (q == 0) Bn[nf].x = o;
+        if (q == 1) Bn[nf].y = o;
+        if (q == 2) Bn[nf].z = o;
+        if (q == 3) Bn[nf].w = o;
+    };
+    // MFMAs of the current step (one-hot fragments Bc), with the VALU that
+    // builds the next step's fragments (into Bn, the other buffer) placed one
+    // dword after each MFMA from the fifth on, so the MFMA pipe never waits
+    // for a run of VALU; then A of the next step.  Scheduling barriers pin
+    // the order (left to itself the compiler issues most MFMAs first).
+    auto step = [&](const uint4 *Bc, uint4 *Bn) {
+        constexpr int NP = 4 * NF;   // dwords of the next fragments
+        uint32_t y[NF];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 4; rb++)
 #pragma unroll
             for (int c = 0; c < NC; c++)
 #pragma unroll
-                for (int nf = 0; nf < NF; nf++)
-                    acc[rb][nf] = mma<BT>(Ac[rb][c], B[nf], acc[rb][nf]);
-        build_b();
+                for (int nf = 0; nf < NF; nf++) {
+                    const int i = (rb * NC + c) * NF + nf;
+                    acc[rb][nf] = mma<BT>(Ac[rb][c], Bc[nf], acc[rb][nf]);
+                    const int p = i - 4;
+                    if (p >= 0 && p < NP) {
+                        const int pf = p / 4, pq = p % 4;
+                        if constexpr (NIB)
+                            if (pq == 0) y[pf] = Lw[pf] ^ ((gg[pf] & 0xFu) * 0x11111111u);
+                        onehot_piece(Bn, pf, pq, NIB ? y[pf] : 0u);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+        for (int p = 4 * NC * NF - 4; p < NP; p++) {   // left over when NC = 1
+            const int pf = p / 4, pq = p % 4;
+            if constexpr (NIB)
+                if (pq == 0) y[pf] = Lw[pf] ^ ((gg[pf] & 0xFu) * 0x11111111u);
+            onehot_piece(Bn, pf, pq, NIB ? y[pf] : 0u);
+        }
 #pragma unroll
         for (int rb = 0; rb < 4; rb++)
 #pragma unroll
             for (int c = 0; c < NC; c++) Ac[rb][c] = An[rb][c];
-        // first half of the MFMAs alone, then one MFMA per three VALU
-#pragma unroll
-        for (int i = 0; i < 2 * NF * NC; i++) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-#pragma unroll
-        for (int i = 0; i < 2 * NF * NC; i++) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-        }
         __builtin_amdgcn_sched_barrier(0);
     };
     // Block kb from (cA, cL); the copy of block kb + 1 into (nA, nL) was
@@ -683,16 +717,16 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     // every address stays in range and the code stays branch-free.
     auto block = [&](int64_t kb, uint4 *cA, uint4 *cL, const uint4 *nA, const uint4 *nL) {
         load_step(cA, cL, 1);
-        step();
+        step(BX[0], BX[1]);
         load_step(cA, cL, 2);
-        step();
+        step(BX[1], BX[0]);
         load_step(cA, cL, 3);
-        step();
+        step(BX[0], BX[1]);
         __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed
         __syncthreads();                 // ... and every wave's; reads of cA done
         stage(kb + 2 < kb1 ? kb + 2 : kb1 - 1, cA, cL);
         load_step(nA, nL, 0);
-        step();
+        step(BX[1], BX[0]);
         // The next block's A fragments were read a whole step ago; saying so
         // here keeps the wait for them out of the loop's first MFMAs (the
         // compiler cannot track LDS reads across the loop's back edge).
@@ -708,7 +742,7 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
     __syncthreads();
     stage(kb0 + 1, sA1, sL1);
     load_step(sA0, sL0, 0);
-    build_b();
+    build_b(BX[0]);
 #pragma unroll
     for (int rb = 0; rb < 4; rb++)
 #pragma unroll
