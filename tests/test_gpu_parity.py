@@ -596,6 +596,34 @@ def test_permanova_constant_matrix_ties(ps, path, sizes, c):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-9
 
 
+# More groups than the FP64 pass keeps weights for in LDS (1,024): the
+# samples and the recheck then read each column label's weight from global
+# memory, before the next tile's loads are issued.  Group sizes 1..3, so many
+# shuffles land near the observed statistic's neighbourhood only by chance;
+# p, F and every s_W must still match the oracle.
+@pytest.mark.parametrize("path", ["plain_f32", "mfma_split_bf16"])
+def test_permanova_more_groups_than_lds_weights(ps, path):
+    import torch
+    k, P, seed = 1100, 99, 77
+    rng = np.random.default_rng(1100)
+    sizes = rng.integers(1, 4, size=k)
+    n = int(sizes.sum())
+    base = np.repeat(np.arange(k, dtype=np.int32), sizes)
+    rng.shuffle(base)
+    D = synth.uniform_matrix(n, 31)
+    ref = oracle.permanova(D, base, P, seed)
+    ps.pstat_set_path(path)
+    Dd, bd = to_dev(D, base)
+    sw = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    res, rechecked = ps.pstat_permanova(Dd, bd, k, P, seed, sW_all=sw)
+    ps.pstat_set_path("auto")
+    res = res.cpu().numpy()
+    assert max_rel(sw.cpu().numpy()[1:], ref["sW_perm"]) <= TOL[path]
+    assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
+    assert res[1] == ref["p"], (path, res[1], ref["p"], rechecked)
+    assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+
+
 # (3) Near ties in bulk: entries of 0.5 and its FP32 neighbours, so every
 # permutation's s_W lies within a few units of 1e-8 (relative) of every
 # other -- about the MFMA forms' own error -- and most of the shuffles fall
