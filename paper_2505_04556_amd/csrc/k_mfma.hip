@@ -922,11 +922,15 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     pl.n_pad = round_up(n, kPanel);
     pl.panels = pl.n_pad / kPanel;
     pl.kb_total = pl.n_pad / kKBlock;
-    // Default K chunk: 1,024 columns, or 2,048 from 128 panels (n > 16,384)
-    // on, where halving the per-item epilogues outweighs the FP64 recheck of
-    // the few more near ties the longer FP32 sums bring (whole tests at
-    // n = 25,000 and 100,000: 4% and 3% faster; at n = 10,000 within 1%)
-    int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock : (pl.panels >= 128 ? 32 : 16);
+    // Default K chunk: 2,048 columns from 128 to 1,023 row panels (16,384 <
+    // n <= 130,944), where halving the per-item epilogues outweighs the FP64
+    // recheck of the few more near ties the longer FP32 sums bring (whole
+    // tests at n = 25,000 and 100,000: 4% and 3% faster), else 1,024: at
+    // n = 10,000 the two are within 1%, and at n = 229,376 the wider band
+    // doubled the near ties (49 against 28 groupings rechecked) and their
+    // FP64 passes cost more than the kernel saved (355 against ~320 ms)
+    int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock
+                                 : (pl.panels >= 128 && pl.panels < 1024 ? 32 : 16);
     // the kernel takes K blocks in pairs: every item's length is even
     // (each panel's range [2I, kb_total) has even length)
     if (kc < 2) kc = 2;
