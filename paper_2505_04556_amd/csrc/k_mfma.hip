@@ -503,6 +503,47 @@ __device__ inline uint4 onehot8_nib(uint32_t L, uint32_t gg) {
     return make_uint4(out[0], out[1], out[2], out[3]);
 }
 
+// zs += y[b] where lab[b] == g, zn += y[b] where lab[b] != L, for b = 0..3
+// in order: eight compares write lane masks, then each add runs under its
+// mask in EXEC (the sums are those of the selects, term by term).  Every lane
+// must be active on entry.
+__device__ inline void masked_pair4(float &zs, float &zn, uint32_t g, uint32_t L,
+                                    const uint32_t *lab, const float *y) {
+    uint64_t e0, e1, e2, e3, m0, m1, m2, m3, sv;
+    asm volatile(
+        "v_cmp_eq_u32_e64 %[e0], %[g], %[l0]\n"
+        "v_cmp_eq_u32_e64 %[e1], %[g], %[l1]\n"
+        "v_cmp_eq_u32_e64 %[e2], %[g], %[l2]\n"
+        "v_cmp_eq_u32_e64 %[e3], %[g], %[l3]\n"
+        "v_cmp_ne_u32_e64 %[m0], %[L], %[l0]\n"
+        "v_cmp_ne_u32_e64 %[m1], %[L], %[l1]\n"
+        "v_cmp_ne_u32_e64 %[m2], %[L], %[l2]\n"
+        "v_cmp_ne_u32_e64 %[m3], %[L], %[l3]\n"
+        "s_mov_b64 %[sv], exec\n"
+        "s_mov_b64 exec, %[e0]\n"
+        "v_add_f32 %[zs], %[zs], %[y0]\n"
+        "s_mov_b64 exec, %[m0]\n"
+        "v_add_f32 %[zn], %[zn], %[y0]\n"
+        "s_mov_b64 exec, %[e1]\n"
+        "v_add_f32 %[zs], %[zs], %[y1]\n"
+        "s_mov_b64 exec, %[m1]\n"
+        "v_add_f32 %[zn], %[zn], %[y1]\n"
+        "s_mov_b64 exec, %[e2]\n"
+        "v_add_f32 %[zs], %[zs], %[y2]\n"
+        "s_mov_b64 exec, %[m2]\n"
+        "v_add_f32 %[zn], %[zn], %[y2]\n"
+        "s_mov_b64 exec, %[e3]\n"
+        "v_add_f32 %[zs], %[zs], %[y3]\n"
+        "s_mov_b64 exec, %[m3]\n"
+        "v_add_f32 %[zn], %[zn], %[y3]\n"
+        "s_mov_b64 exec, %[sv]\n"
+        : [zs] "+v"(zs), [zn] "+v"(zn), [e0] "=&s"(e0), [e1] "=&s"(e1), [e2] "=&s"(e2),
+          [e3] "=&s"(e3), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3),
+          [sv] "=&s"(sv)
+        : [g] "v"(g), [L] "v"(L), [l0] "v"(lab[0]), [l1] "v"(lab[1]), [l2] "v"(lab[2]),
+          [l3] "v"(lab[3]), [y0] "v"(y[0]), [y1] "v"(y[1]), [y2] "v"(y[2]), [y3] "v"(y[3]));
+}
+
 template <int DT>
 __device__ inline f32x16 mma(uint4 a, uint4 b, f32x16 c) {
     if (DT == 1)
@@ -810,12 +851,9 @@ __device__ __attribute__((always_inline)) inline void mfma_unit(
                     lab4[2] = l4[rb][a].y & 0xFFFFu;
                     lab4[3] = l4[rb][a].y >> 16;
                 }
-#pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const float y = acc[rb][nf][4 * a + b];
-                    zs += (lab4[b] == g) ? y : 0.0f;
-                    zn += (lab4[b] != (uint32_t)Lg) ? y : 0.0f;
-                }
+                const float y4[4] = {acc[rb][nf][4 * a], acc[rb][nf][4 * a + 1],
+                                     acc[rb][nf][4 * a + 2], acc[rb][nf][4 * a + 3]};
+                masked_pair4(zs, zn, g, (uint32_t)Lg, lab4, y4);
             }
         }
         zs += __shfl_xor(zs, 32);
