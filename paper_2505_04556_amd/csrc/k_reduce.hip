@@ -181,29 +181,32 @@ __global__ __launch_bounds__(256) void k_sum_fixed(const double *__restrict__ x,
     if (threadIdx.x == 0) *out = t;
 }
 
-// vnot[p] = sum over i with lab[p][i] != *L of v[i]: kVnotRows groupings per
+// vnot[p] = sum over i with lab[p][i] != *L of v[i]: ROWS groupings per
 // work-group (each v entry is read once for all of them), eight labels (16
 // bytes) per thread and step, fixed order.  Rows are read to their padded
-// length (a multiple of 128): the pad entries' v is zero.
-constexpr int kVnotRows = 8;
+// length (a multiple of 128): the pad entries' v is zero.  A grouping's sum
+// does not depend on ROWS: the launch takes 2 rows per work-group for a few
+// thousand groupings (enough work-groups to fill the device: 0.22 -> 0.07 ms
+// for 1,000 groupings at n = 100,000) and 8 above.
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_vnot(const uint16_t *__restrict__ lab, int64_t stride,
                                               int64_t n_pad, int64_t P,
                                               const int32_t *__restrict__ Lp,
                                               const double *__restrict__ v,
                                               double *__restrict__ vnot) {
-    __shared__ double red[4][kVnotRows];
+    __shared__ double red[4][ROWS];
     const uint32_t L = (uint32_t)*Lp;
-    for (int64_t p0 = (int64_t)blockIdx.x * kVnotRows; p0 < P;
-         p0 += (int64_t)gridDim.x * kVnotRows) {
-        double a[kVnotRows];
+    for (int64_t p0 = (int64_t)blockIdx.x * ROWS; p0 < P;
+         p0 += (int64_t)gridDim.x * ROWS) {
+        double a[ROWS];
 #pragma unroll
-        for (int q = 0; q < kVnotRows; q++) a[q] = 0.0;
+        for (int q = 0; q < ROWS; q++) a[q] = 0.0;
         for (int64_t c = threadIdx.x; c < n_pad / 8; c += 256) {
             const double2 *vv = reinterpret_cast<const double2 *>(v + c * 8);
             const double2 v0 = vv[0], v1 = vv[1], v2 = vv[2], v3 = vv[3];
             const double x[8] = {v0.x, v0.y, v1.x, v1.y, v2.x, v2.y, v3.x, v3.y};
 #pragma unroll
-            for (int q = 0; q < kVnotRows; q++) {
+            for (int q = 0; q < ROWS; q++) {
                 if (p0 + q >= P) break;
                 const uint4 l = reinterpret_cast<const uint4 *>(lab + (p0 + q) * stride)[c];
                 const uint32_t lw[4] = {l.x, l.y, l.z, l.w};
@@ -213,13 +216,13 @@ __global__ __launch_bounds__(256) void k_vnot(const uint16_t *__restrict__ lab, 
             }
         }
 #pragma unroll
-        for (int q = 0; q < kVnotRows; q++) {
+        for (int q = 0; q < ROWS; q++) {
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) a[q] += __shfl_xor(a[q], o);
             if (threadIdx.x % 64 == 0) red[threadIdx.x / 64][q] = a[q];
         }
         __syncthreads();
-        if (threadIdx.x < kVnotRows && p0 + threadIdx.x < P)
+        if (threadIdx.x < ROWS && p0 + threadIdx.x < P)
             vnot[p0 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
                                       red[2][threadIdx.x]) + red[3][threadIdx.x];
         __syncthreads();
@@ -401,10 +404,15 @@ void launch_complement_sums(const Complement &cx, int64_t n, hipStream_t s) {
 void launch_vnot(const Complement &cx, const uint16_t *lab, int64_t stride, int64_t n, int64_t P,
                  hipStream_t s) {
     if (P <= 0) return;
-    const int64_t groups = ceil_div(P, kVnotRows);
+    const int rows = P <= 4096 ? 2 : 8;
+    const int64_t groups = ceil_div(P, rows);
     const unsigned g = (unsigned)(groups < 65535 ? groups : 65535);
-    hipLaunchKernelGGL(k_vnot, dim3(g), dim3(256), 0, s, lab, stride, round_up(n, 128), P,
-                       (const int32_t *)cx.L, (const double *)cx.v, cx.vnot);
+    if (rows == 2)
+        hipLaunchKernelGGL(k_vnot<2>, dim3(g), dim3(256), 0, s, lab, stride, round_up(n, 128), P,
+                           (const int32_t *)cx.L, (const double *)cx.v, cx.vnot);
+    else
+        hipLaunchKernelGGL(k_vnot<8>, dim3(g), dim3(256), 0, s, lab, stride, round_up(n, 128), P,
+                           (const int32_t *)cx.L, (const double *)cx.v, cx.vnot);
 }
 
 void launch_F(const double *sW, int64_t count, const double *sT, int64_t n, int32_t k,
