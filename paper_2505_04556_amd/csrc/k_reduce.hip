@@ -62,6 +62,7 @@ __global__ void k_reduce_slices(double *__restrict__ tmp, int64_t total, int64_t
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
+#pragma unroll 8
         for (int64_t q = 0; q < slices; q++) s += tmp[(1 + q) * total + e];
         tmp[e] = s;
     }
@@ -136,8 +137,10 @@ __global__ void k_complement_slices(const double *__restrict__ rcs, int64_t n_pa
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t I = i / 128, kj = i / 64;
         double a = 0.0, b = 0.0;
+#pragma unroll 8
         for (int64_t kb = 2 * I + y; kb < kb_total; kb += kComplementSlices)
             a += rcs[(I * (kb_total - I + 1) + kb - 2 * I) * 192 + i % 128];
+#pragma unroll 8
         for (int64_t J = y; 2 * J <= kj; J += kComplementSlices)
             b += rcs[(J * (kb_total - J + 1) + kj - 2 * J) * 192 + 128 + i % 64];
         part[(y * 2) * n_pad + i] = a;
@@ -176,6 +179,7 @@ __global__ __launch_bounds__(256) void k_sum_fixed(const double *__restrict__ x,
                                                    double *__restrict__ out) {
     __shared__ double red[4];
     double a = 0.0;
+#pragma unroll 8
     for (int64_t i = threadIdx.x; i < count; i += 256) a += x[i];
     const double t = block_sum_fixed(a, red);
     if (threadIdx.x == 0) *out = t;
