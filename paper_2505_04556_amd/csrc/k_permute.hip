@@ -100,9 +100,18 @@ __device__ inline uint32_t rotate_row(uint32_t v, int r) {
     return v;
 }
 
-// The whole wave rotated by one lane (DPP wave_ror:1).
-__device__ inline uint32_t rotate_wave1(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+// OR over the 64 lanes of the wave, the same value in every lane: prefix ORs
+// within each row of 16 lanes (shifts by 1, 2, 4, 8), row 0's and row 2's
+// totals carried into the next row, lane 31's into rows 2 and 3, and lane
+// 63's result read out.
+__device__ inline uint32_t or_wave(uint32_t v) {
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // The ballot bits of this lane's group of B lanes.
@@ -338,32 +347,53 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
         if (lowtop < 1) lowtop = 1;
         // a partner on a later step's top index (top - s for some s > t)
         bool conflict = real && j >= lowtop && j < it;
-        // Two equal partners: every other lane's partner key (idle lanes and
-        // self-swaps carry ~t, which no partner or other key equals) is
-        // compared with this lane's; a zero of key ^ other marks it, and the
-        // minimum over the group is kept with one three-operand min per two
-        // lanes rotated in.
-        const uint32_t key = real ? (uint32_t)j : ~(uint32_t)t;
-        uint32_t mn = 0xFFFFFFFFu;
-        uint32_t kr = key;
-        uint32_t prev = 0xFFFFFFFFu;
+        // Two equal partners (`shared`).
+        bool shared;
+        if constexpr (B == 16) {
+            // every other lane's partner key (idle lanes and self-swaps carry
+            // ~t, which no partner or other key equals) is compared with this
+            // lane's; a zero of key ^ other marks it, and the minimum over
+            // the group is kept with one three-operand min per two lanes
+            // rotated in
+            const uint32_t key = real ? (uint32_t)j : ~(uint32_t)t;
+            uint32_t mn = 0xFFFFFFFFu;
+            uint32_t prev = 0xFFFFFFFFu;
 #pragma unroll
-        for (int r = 1; r < B; r++) {
-            uint32_t ko;
-            if constexpr (B == 16) {
-                ko = rotate_row(key, r);
-            } else {
-                kr = rotate_wave1(kr);      // B == 64: every lane in turn
-                ko = kr;
+            for (int r = 1; r < B; r++) {
+                const uint32_t ko = rotate_row(key, r);
+                if (r % 2 == 1) {
+                    prev = ko ^ key;
+                } else {
+                    mn = min(min(mn, prev), ko ^ key);
+                    prev = 0xFFFFFFFFu;
+                }
             }
-            if (r % 2 == 1) {
-                prev = ko ^ key;
-            } else {
-                mn = min(min(mn, prev), ko ^ key);
-                prev = 0xFFFFFFFFu;
+            shared = min(mn, prev) == 0;
+        } else {
+            // B == 64: the lanes with real swaps whose partners agree with
+            // this lane's in the low kMatchBits bits, as the AND over those
+            // bits of the ballot of lanes with the bit set (or its
+            // complement); a lane is marked when any lane but itself is
+            // left.  Partners that differ only above those bits are marked
+            // too: their swaps just keep step order with the other marked
+            // ones, which gives the same result.
+            constexpr int kMatchBits = 16;
+            const uint64_t any = __ballot(real);
+            uint32_t m_lo = (uint32_t)any, m_hi = (uint32_t)(any >> 32);
+            uint64_t on[kMatchBits];
+#pragma unroll
+            for (int b = 0; b < kMatchBits; b++) on[b] = __ballot((((uint32_t)j >> b) & 1u) != 0);
+#pragma unroll
+            for (int b = 0; b < kMatchBits; b++) {
+                // all ones where bit b of j is set
+                const uint32_t e = (uint32_t)(((int32_t)((uint32_t)j << (31 - b))) >> 31);
+                m_lo &= (uint32_t)on[b] ^ ~e;
+                m_hi &= (uint32_t)(on[b] >> 32) ^ ~e;
             }
+            if (lane < 32) m_lo &= ~(1u << lane);
+            else m_hi &= ~(1u << (lane - 32));
+            shared = real && (m_lo | m_hi) != 0;
         }
-        mn = min(mn, prev);
         // A step whose top index is another step's partner: the partners on
         // top indices set bit s (top - j) of a group-wide mask.
         uint32_t hit;
@@ -376,21 +406,18 @@ __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict
             hm |= rotate_row(hm, 1);
             hit = (hm >> t) & 1u;
         } else {
-            // B == 64: a 64-bit mask, OR-reduced over the wave by a butterfly
+            // B == 64: a 64-bit mask, OR-reduced over the wave
             uint32_t lo = 0, hi = 0;
             if (conflict) {
                 const uint32_t s = (uint32_t)(top - j);
                 lo = s < 32 ? 1u << s : 0u;
                 hi = s < 32 ? 0u : 1u << (s - 32);
             }
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                lo |= (uint32_t)__shfl_xor((int)lo, off);
-                hi |= (uint32_t)__shfl_xor((int)hi, off);
-            }
+            lo = or_wave(lo);
+            hi = or_wave(hi);
             hit = ((t < 32 ? lo >> t : hi >> (t - 32))) & 1u;
         }
-        conflict = (conflict || mn == 0 || hit != 0) && valid;
+        conflict = (conflict || shared || hit != 0) && valid;
 
         // swaps without conflict, all at once; the next batch's draw is
         // computed while their reads are in flight (a scheduling barrier

@@ -63,6 +63,10 @@ def test_device_generators_match_host(ps):
     # lanes each beyond that; nibbles and bytes with 16 lanes each
     (100_000, 2, 40, 13), (60_000, 3, 24, 13), (10_000, 3, 400, 13),
     (5_000, 3, 5_000, 13), (5_000, 9, 5_000, 13), (5_000, 100, 5_000, 13),
+    # a whole wave per permutation over partners above 2^16, where partners
+    # that agree in their low 16 bits also count as conflicting (a few
+    # percent of batches), with two and with three arrays per CU
+    (216_000, 3, 300, 13), (216_000, 3, 520, 13),
 ])
 def test_permute_bit_exact(ps, n, maxlab, P, seed):
     import torch
