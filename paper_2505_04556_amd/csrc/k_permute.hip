@@ -295,16 +295,17 @@ using CrumbStore = PackedStore<2>;
 // blockDim.x / 64 waves per work-group, arrays in dynamic LDS as S stores them;
 // permutation p goes to row p of `out` (O = int32 rows of n labels, or u16
 // rows of `ostride` entries padded with kPadLabel).
+// This launch covers permutations pfirst .. P - 1.
 template <typename S, int B, typename O>
 __global__ __launch_bounds__(256) void k_permute_batch(const int32_t *__restrict__ base, int64_t n,
-                                                       int64_t P, uint64_t seed, int apw, int vec,
-                                                       O *__restrict__ out, int64_t ostride,
-                                                       int ovec) {
+                                                       int64_t pfirst, int64_t P, uint64_t seed,
+                                                       int apw, int vec, O *__restrict__ out,
+                                                       int64_t ostride, int ovec) {
     static_assert(B == 16 || B == 64, "lanes per permutation");
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ppg = (nthr / 64) * apw;                // permutations per work-group (apw per wave)
-    const int64_t p0 = (int64_t)blockIdx.x * ppg;
+    const int64_t p0 = pfirst + (int64_t)blockIdx.x * ppg;
     int live = ppg;
     if (p0 + live > P) live = (int)(P - p0);
     S::fill(smem, base, n, live, vec, tid, nthr);
@@ -557,6 +558,23 @@ int launch_lds(const int32_t *base, int64_t n, int64_t P, uint64_t seed, int32_t
     return 0;
 }
 
+// One launch of the batched form over permutations pfirst .. plast - 1.
+template <typename S, int B, typename O>
+void launch_part(const int32_t *base, int64_t n, int64_t pfirst, int64_t plast, uint64_t seed,
+                 O *out, int64_t ostride, int pw, int64_t waves, size_t lds_limit, hipStream_t s) {
+    const int64_t ppg = waves * pw;
+    const size_t bytes = (size_t)ppg * S::row_bytes(n) + S::spare_bytes();
+    const int64_t blocks = ceil_div(plast - pfirst, ppg);
+    // 16-byte loads of the base labels; 16-byte stores of whole rows' words
+    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0);
+    const int ovec = (uintptr_t)out % 16 == 0 &&
+                     (sizeof(O) == 4 ? n % 4 == 0 : ostride % 8 == 0);
+    allow_lds(k_permute_batch<S, B, O>, lds_limit);
+    hipLaunchKernelGGL((k_permute_batch<S, B, O>), dim3((unsigned)blocks),
+                       dim3((unsigned)(64 * waves)), bytes, s, base, n, pfirst, plast, seed, pw,
+                       vec, out, ostride, ovec);
+}
+
 // Batched form: up to four waves per work-group (one per SIMD), up to 16
 // arrays; B = 16 lanes per permutation and 1, 2 or 4 arrays per wave when at
 // least four arrays fit, else B = 64 and one array per wave.  Work-groups
@@ -571,8 +589,7 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
     if (fit < 1) return 1;
     if (fit > 16) fit = 16;
     if (fit > P) fit = P;
-    int B, pw;
-    int64_t waves;
+    const int64_t cus = n_cu > 0 ? n_cu : 256;
     // Arrays a CU holds with one per wave (64 lanes each): work-groups of w
     // waves, as many as its LDS takes.  When that runs every permutation at
     // once, each gets a whole wave (the shortest chain of batches); with
@@ -581,36 +598,27 @@ int launch_batch(const int32_t *base, int64_t n, int64_t P, uint64_t seed, O *ou
     int64_t w64 = per_cu < 4 ? per_cu : 4;
     for (int64_t w = w64; w >= 1; --w)
         if ((per_cu / w) * w > (per_cu / w64) * w64) w64 = w;
-    if (fit >= 4 && P > (int64_t)(n_cu > 0 ? n_cu : 256) * per_cu) {
-        B = 16;
-        pw = (int)ceil_div(fit, 4);
-        if (pw == 3) pw = 2;                     // 1, 2 or 4 arrays per wave
-        waves = fit / pw;
-        if (waves > 4) waves = 4;
-    } else {
-        B = 64;
-        pw = 1;
-        waves = w64;
+    if (!(fit >= 4 && P > cus * per_cu)) {
+        launch_part<S, 64, O>(base, n, 0, P, seed, out, ostride, 1, w64, lds_limit, s);
+        return 0;
     }
+    int pw = (int)ceil_div(fit, 4);
+    if (pw == 3) pw = 2;                         // 1, 2 or 4 arrays per wave
+    int64_t waves = fit / pw;
+    if (waves > 4) waves = 4;
+    // The permutations the device runs at once with 16 lanes each; a last
+    // partial round small enough to run with a whole wave per permutation
+    // does so in a launch of its own, a quarter of the batches long.
     const int64_t ppg = waves * pw;
-    const size_t bytes = (size_t)ppg * row + spare;
-    const int64_t blocks = ceil_div(P, ppg);
-    // 16-byte loads of the base labels; 16-byte stores of whole rows' words
-    const int vec = (n % 4 == 0) && ((uintptr_t)base % 16 == 0);
-    const int ovec = (uintptr_t)out % 16 == 0 &&
-                     (sizeof(O) == 4 ? n % 4 == 0 : ostride % 8 == 0);
-    const dim3 grid((unsigned)blocks), block((unsigned)(64 * waves));
-#define PSTAT_BATCH_CASE(B_)                                                                     \
-    if (B == B_) {                                                                               \
-        allow_lds(k_permute_batch<S, B_, O>, lds_limit);                                         \
-        hipLaunchKernelGGL((k_permute_batch<S, B_, O>), grid, block, bytes, s, base, n, P, seed,  \
-                           pw, vec, out, ostride, ovec);                                         \
-        return 0;                                                                                \
-    }
-    PSTAT_BATCH_CASE(16)
-    PSTAT_BATCH_CASE(64)
-#undef PSTAT_BATCH_CASE
-    return 1;
+    int64_t groups = (int64_t)(lds_limit / ((size_t)ppg * row + spare));
+    if (groups < 1) groups = 1;
+    const int64_t round = cus * groups * ppg;
+    const int64_t rest = P % round;
+    const int64_t split = P > round && rest > 0 && rest <= cus * per_cu ? P - rest : P;
+    launch_part<S, 16, O>(base, n, 0, split, seed, out, ostride, pw, waves, lds_limit, s);
+    if (split < P)
+        launch_part<S, 64, O>(base, n, split, P, seed, out, ostride, 1, w64, lds_limit, s);
+    return 0;
 }
 
 } // namespace

@@ -67,6 +67,10 @@ def test_device_generators_match_host(ps):
     # that agree in their low 16 bits also count as conflicting (a few
     # percent of batches), with two and with three arrays per CU
     (216_000, 3, 300, 13), (216_000, 3, 520, 13),
+    # more permutations than the device runs at once with 16 lanes each: the
+    # last partial round with a whole wave per permutation (9,999), and a
+    # rest too large for that, left with 16 lanes (13,192)
+    (10_000, 5, 9_999, 13), (10_000, 5, 13_192, 13),
 ])
 def test_permute_bit_exact(ps, n, maxlab, P, seed):
     import torch
