@@ -65,7 +65,7 @@ def test_device_generators_match_host(ps):
     (5_000, 3, 5_000, 13), (5_000, 9, 5_000, 13), (5_000, 100, 5_000, 13),
     # a whole wave per permutation over partners above 2^16, where partners
     # that agree in their low 16 bits also count as conflicting (a few
-    # percent of batches), with two and with three arrays per CU
+    # percent of batches)
     (216_000, 3, 300, 13), (216_000, 3, 520, 13),
     # more permutations than the device runs at once with 16 lanes each: the
     # last partial round with a whole wave per permutation (9,999), and a
