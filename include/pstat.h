@@ -105,8 +105,9 @@ int pstat_resolve_path(int path, int64_t n, int32_t n_groups);
  * values (0 = keep the tuned value).  Plain paths: tile = square tile edge
  * (32 or 64), batch = permutation lanes per work-group (64, 128 or 256).  MFMA
  * paths: tile = K-chunk length in columns (multiple of 64, rounded up to a
- * multiple of 128; 0 = the library's choice: 2,048 columns for 16,384 < n <=
- * 130,944, else 1,024), batch = N columns per work-group (256 or 512).
+ * multiple of 128; 0 = the library's choice: 2,048 columns for 16,256 < n <=
+ * 130,944, 1,536 for 8,064 < n <= 16,256, else 1,024), batch = N columns per
+ * work-group (256 or 512).
  * Invalid values give PSTAT_EINVAL. */
 int pstat_set_tuning(int path, int tile, int batch);
 

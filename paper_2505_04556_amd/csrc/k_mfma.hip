@@ -960,15 +960,19 @@ MfmaPlan mfma_plan(int64_t n, int64_t P, int32_t k, int dtype, int kchunk_cols, 
     pl.n_pad = round_up(n, kPanel);
     pl.panels = pl.n_pad / kPanel;
     pl.kb_total = pl.n_pad / kKBlock;
-    // Default K chunk: 2,048 columns from 128 to 1,023 row panels (16,384 <
+    // Default K chunk: 2,048 columns from 128 to 1,023 row panels (16,256 <
     // n <= 130,944), where halving the per-item epilogues outweighs the FP64
     // recheck of the few more near ties the longer FP32 sums bring (whole
-    // tests at n = 25,000 and 100,000: 4% and 3% faster), else 1,024: at
-    // n = 10,000 the two are within 1%, and at n = 229,376 the wider band
-    // doubled the near ties (49 against 28 groupings rechecked) and their
-    // FP64 passes cost more than the kernel saved (355 against ~320 ms)
+    // tests at n = 25,000 and 100,000: 4% and 3% faster); 1,536 from 64 to
+    // 127 panels (8,064 < n <= 16,256; at n = 10,000 2% faster than 1,024,
+    // 2,048 slower again); else 1,024: at n = 229,376 the wider band doubled
+    // the near ties (49 against 28 groupings rechecked) and their FP64
+    // passes cost more than the kernel saved (355 against ~320 ms)
     int64_t kc = kchunk_cols > 0 ? kchunk_cols / kKBlock
-                                 : (pl.panels >= 128 && pl.panels < 1024 ? 32 : 16);
+                 : pl.panels >= 1024 ? 16
+                 : pl.panels >= 128  ? 32
+                 : pl.panels >= 64   ? 24
+                                     : 16;
     // the kernel takes K blocks in pairs: every item's length is even
     // (each panel's range [2I, kb_total) has even length)
     if (kc < 2) kc = 2;
