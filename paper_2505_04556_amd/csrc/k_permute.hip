@@ -21,10 +21,11 @@
 // shifts every later step of its batch onto another draw, so such a batch is
 // replayed by the group's first lane in order, rejections included.  Each
 // batch consumes B draws per permutation either way, so the result is
-// bit-identical to the one-lane-per-permutation form.  Labels below 16 are
-// stored four bits to an entry (eight per LDS word, swapped with atomic xor),
-// else one byte or one u16; the output is int32 rows, or u16 rows padded to
-// a stride (the MFMA forms' staged layout).
+// bit-identical to the one-lane-per-permutation form.  Labels below 4 are
+// stored two bits to an entry (sixteen per LDS word) and labels below 16 four
+// bits (eight per word), both swapped with atomic xor, else one byte or one
+// u16; the output is int32 rows, or u16 rows padded to a stride (the MFMA
+// forms' staged layout).
 //
 // Fallbacks: one lane per permutation with the arrays in LDS, or in place in
 // the output when not even one array fits.
