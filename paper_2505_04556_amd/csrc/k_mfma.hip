@@ -292,14 +292,19 @@ __global__ __launch_bounds__(256) void k_prepass(const float *__restrict__ mat, 
                         d2[ps] = kept(ps, e) ? (double)x * (double)x : 0.0;
                         st += d2[ps];
                     }
+                    static_assert(Q % 2 == 0, "groupings in pairs");
 #pragma unroll
-                    for (int q = 0; q < Q; q++) {
+                    for (int q = 0; q < Q; q += 2) {
                         const uint4 ra = *reinterpret_cast<const uint4 *>(&rrow[q][rq][0]);
                         const uint4 rb = *reinterpret_cast<const uint4 *>(&rrow[q][rq][4]);
-                        const uint32_t rl[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-                        double sum = 0.0;
-                        masked_add8(sum, rcol[q][cq + e], rl, d2);
-                        acc[q] = __builtin_fma(sum, rw[q][cq + e], acc[q]);
+                        const uint4 sa = *reinterpret_cast<const uint4 *>(&rrow[q + 1][rq][0]);
+                        const uint4 sb = *reinterpret_cast<const uint4 *>(&rrow[q + 1][rq][4]);
+                        const uint32_t rl0[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+                        const uint32_t rl1[8] = {sa.x, sa.y, sa.z, sa.w, sb.x, sb.y, sb.z, sb.w};
+                        double s0 = 0.0, s1 = 0.0;
+                        masked_add8_pair(s0, rcol[q][cq + e], rl0, s1, rcol[q + 1][cq + e], rl1, d2);
+                        acc[q] = __builtin_fma(s0, rw[q][cq + e], acc[q]);
+                        acc[q + 1] = __builtin_fma(s1, rw[q + 1][cq + e], acc[q + 1]);
                     }
                 }
             }
