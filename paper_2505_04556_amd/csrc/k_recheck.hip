@@ -168,27 +168,37 @@ __global__ __launch_bounds__(256) void k_sw_few(const float *__restrict__ mat, i
         double d2[kStrip];
 #pragma unroll
         for (int u = 0; u < kStrip; u++) d2[u] = (double)b.dn[u] * (double)b.dn[u];
+        static_assert(EQ % 2 == 0, "groupings in pairs");
 #pragma unroll
-        for (int q = 0; q < EQ; q++) {
-            const uint4 *rl = reinterpret_cast<const uint4 *>(&srow[wave][q][0]);
-            uint32_t li[kStrip];
+        for (int q = 0; q < EQ; q += 2) {
+            uint32_t li[2][kStrip];
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const uint4 r4 = rl[v];
-                li[4 * v] = r4.x;
-                li[4 * v + 1] = r4.y;
-                li[4 * v + 2] = r4.z;
-                li[4 * v + 3] = r4.w;
+            for (int h = 0; h < 2; h++) {
+                const uint4 *rl = reinterpret_cast<const uint4 *>(&srow[wave][q + h][0]);
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const uint4 r4 = rl[v];
+                    li[h][4 * v] = r4.x;
+                    li[h][4 * v + 1] = r4.y;
+                    li[h][4 * v + 2] = r4.z;
+                    li[h][4 * v + 3] = r4.w;
+                }
             }
-            const uint32_t v = b.ln[q];
-            double wc;
-            if constexpr (WL)
-                wc = weight(v, sw[v < (uint32_t)k ? v : 0u]);
-            else
-                wc = b.wg[q];
-            double sum = 0.0;
-            masked_add16(sum, v, li, d2);
-            acc[q] = __builtin_fma(sum, wc, acc[q]);
+            double wc[2];
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint32_t v = b.ln[q + h];
+                if constexpr (WL)
+                    wc[h] = weight(v, sw[v < (uint32_t)k ? v : 0u]);
+                else
+                    wc[h] = b.wg[q + h];
+            }
+            // the 16 terms of each grouping in order, eight per call
+            double s0 = 0.0, s1 = 0.0;
+            masked_add8_pair(s0, b.ln[q], li[0], s1, b.ln[q + 1], li[1], d2);
+            masked_add8_pair(s0, b.ln[q], li[0] + 8, s1, b.ln[q + 1], li[1] + 8, d2 + 8);
+            acc[q] = __builtin_fma(s0, wc[0], acc[q]);
+            acc[q + 1] = __builtin_fma(s1, wc[1], acc[q + 1]);
         }
     };
     // the run's tiles in order: along the tile row, then the next row
