@@ -3,7 +3,8 @@ permutation counts drawn from fixed seeds, so that the launch plans the
 library picks by size (entry widths, lanes per permutation, a split last
 pass, tile edges, K chunks) meet combinations the hand-picked cases do not.
 Every case is checked against the FP64 CPU oracle: the shuffles bit for bit,
-the whole test by s_W within the form's bound, F, the exact p and s_T."""
+the whole test by s_W within the form's bound, F, the exact p and s_T, and
+the same whole test on the packed strict upper triangle bit for bit."""
 import math
 
 import numpy as np
@@ -75,3 +76,11 @@ def test_permanova_random_shapes(ps, i, path):
     assert max_rel([res[0]], [ref["F_obs"]]) <= 1e-5
     assert res[1] == ref["p"], (path, res[1], ref["p"], rechecked)
     assert max_rel([res[3]], [ref["sT"]]) <= 1e-13
+    # the same test on the packed strict upper triangle: the same bits
+    packed = torch.from_numpy(D[np.triu_indices(n, 1)].copy()).cuda()
+    sw2 = torch.empty(P + 1, dtype=torch.float64, device="cuda")
+    ps.pstat_set_path(path)
+    res2, _ = ps.pstat_permanova(packed, bd, len(sizes), P, seed, sW_all=sw2)
+    ps.pstat_set_path("auto")
+    assert np.array_equal(sw2.cpu().numpy(), sw)
+    assert np.array_equal(res2.cpu().numpy(), res)
